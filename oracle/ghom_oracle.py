@@ -1,0 +1,466 @@
+"""FP64 CPU oracle for Galerkin-FFT homogenization with stress and mixed control.
+
+Method: Lucarini & Segurado, "An algorithm for stress and mixed control in Galerkin
+based FFT homogenization" (arXiv:1901.06531).
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain reference the HIP path is
+checked against.  Only the test-suite, the smoke check and the benchmark's CPU-baseline
+leg may import it; the product library never calls it and shares no code with it.
+
+Everything is computed in float64 with plain NumPy array arithmetic.  The 3-D discrete
+Fourier transform is taken from ``scipy.fft`` (a library primitive); the projection, the
+materials, the conjugate-gradient solve and the Newton loop are written out below in the
+order and notation of the paper.
+
+Conventions (the paper leaves them open; the reading taken is stated where it is used):
+
+* A tensor field is an array of shape ``(9, nx, ny, nz)``; component ``c = 3*i + j`` holds
+  the tensor entry ``(i, j)``.  Internally fields are viewed as ``(3, 3, nx, ny, nz)``.
+* The cell is periodic with edge lengths ``(Lx, Ly, Lz)``; the frequency vector of the
+  integer wave numbers ``(kx, ky, kz)`` is ``xi = (kx/Lx, ky/Ly, kz/Lz)`` (Sec. 2.1,
+  "Projection operator": xi has the dimension of an inverse length; a factor 2*pi would
+  cancel in xi_j xi_l / xi.xi).
+* ``mask[c] = 1`` marks a stress-controlled component IJ (the macroscopic first
+  Piola-Kirchhoff stress is prescribed), ``mask[c] = 0`` a deformation-gradient
+  controlled component ij (Sec. 2.3).
+
+Parity pins: every function here is checked in ``tests/test_oracle_*.py`` against
+brute-force transforms, closed forms, finite differences and invariants.
+"""
+
+from __future__ import annotations
+
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.fft as sfft
+
+WORKERS = max(1, os.cpu_count() or 1)
+
+EYE9 = np.eye(3).reshape(9)
+
+
+class OracleError(RuntimeError):
+    """Base class of the oracle's failure modes."""
+
+
+class DomainError(OracleError):
+    """det F <= 0 somewhere: the hyperelastic laws are undefined."""
+
+
+class BreakdownError(OracleError):
+    """Conjugate gradients met p.Ap <= 0 or a non-finite value."""
+
+
+class NotConvergedError(OracleError):
+    """An iteration cap was reached."""
+
+
+# --------------------------------------------------------------------------------------
+# Fourier grid and the projection operator (Sec. 2.1 eq. 9-10, Sec. 2.2 eq. 19,
+# Sec. 2.3 eq. 22)
+# --------------------------------------------------------------------------------------
+
+def wave_numbers(n: int) -> np.ndarray:
+    """Signed integer wave numbers of an axis of n points, in DFT output order.
+
+    Index k < n/2 is the wave number k, index k > n/2 the wave number k - n; for even n the
+    index n/2 is the Nyquist frequency (kept as -n/2 here; it is zeroed by the projection).
+    """
+    k = np.arange(n)
+    return np.where(k <= (n - 1) // 2, k, k - n)
+
+
+def nyquist_mask(shape) -> np.ndarray:
+    """True at every frequency where some even-length axis sits at its Nyquist index n/2.
+
+    Reading of the paper's "Nyquist frequencies" (eq. 10, 19, 22): the operator is zero
+    wherever ANY even axis is at its highest frequency.  This keeps the projected spectrum
+    Hermitian (real fields map to real fields) and the operator an orthogonal projector.
+    """
+    nx, ny, nz = shape
+    out = np.zeros(shape, dtype=bool)
+    if nx % 2 == 0:
+        out[nx // 2, :, :] = True
+    if ny % 2 == 0:
+        out[:, ny // 2, :] = True
+    if nz % 2 == 0:
+        out[:, :, nz // 2] = True
+    return out
+
+
+def frequency_vectors(shape, lengths=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """xi at every frequency, shape (3, nx, ny, nz): xi_d = k_d / L_d."""
+    ks = [wave_numbers(n) / float(L) for n, L in zip(shape, lengths)]
+    return np.stack(np.meshgrid(*ks, indexing="ij"))
+
+
+def project_spectrum(A_hat: np.ndarray, mask, lengths=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Apply the modified projection G* of eq. (22) to a spectrum, frequency by frequency.
+
+    ``A_hat`` has shape (3, 3, nx, ny, nz).  At xi != 0 (and off the Nyquist set) the
+    compatible part of eq. (8)/(9) is returned: B_ij = delta_ik xi_j xi_l / (xi.xi) A_kl,
+    i.e. each tensor row projected on xi/|xi|.  At Nyquist frequencies B = 0 (eq. 10).  At
+    xi = 0 a stress-controlled component is passed through unchanged (the fourth-order
+    identity of eq. 19) and a deformation-controlled one is set to zero (eq. 10), which is
+    eq. (22).  Full strain control is mask == 0 everywhere, full stress control mask == 1.
+    """
+    shape = A_hat.shape[2:]
+    xi = frequency_vectors(shape, lengths)
+    xi2 = np.einsum("d...,d...->...", xi, xi)
+    null = xi2 == 0.0
+    safe = np.where(null, 1.0, xi2)
+    # row i of A contracted with xi, divided by xi.xi, then outer product with xi
+    row_dot = np.einsum("il...,l...->i...", A_hat, xi) / safe
+    B = np.einsum("i...,j...->ij...", row_dot, xi)
+    B[:, :, nyquist_mask(shape)] = 0.0
+    m = np.asarray(mask, dtype=float).reshape(3, 3)
+    B[:, :, null] = (m[:, :, None] * A_hat[:, :, null])
+    return B
+
+
+def apply_projection(field9: np.ndarray, mask, lengths=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Real-space G*(A) = F^-1{ G*_hat : F{A} } of a real tensor field (eq. 2 with G*)."""
+    shape = field9.shape[1:]
+    A = field9.reshape((3, 3) + shape)
+    A_hat = sfft.fftn(A, axes=(2, 3, 4), workers=WORKERS)
+    B_hat = project_spectrum(A_hat, mask, lengths)
+    B = sfft.ifftn(B_hat, axes=(2, 3, 4), workers=WORKERS)
+    return np.ascontiguousarray(B.real.reshape((9,) + shape))
+
+
+# --------------------------------------------------------------------------------------
+# Hyperelastic materials (Sec. 3.1 Saint Venant-Kirchhoff; compressible neo-Hookean)
+# All functions act on voxel-first arrays of 3x3 matrices, shape (M, 3, 3).
+# --------------------------------------------------------------------------------------
+
+def _voxels(field9: np.ndarray) -> np.ndarray:
+    """(9, nx, ny, nz) -> (N, 3, 3) view-copy, voxel first."""
+    return np.ascontiguousarray(field9.reshape(9, -1).T).reshape(-1, 3, 3)
+
+
+def _field(vox: np.ndarray, shape) -> np.ndarray:
+    """(N, 3, 3) -> (9, nx, ny, nz)."""
+    return np.ascontiguousarray(vox.reshape(-1, 9).T).reshape((9,) + tuple(shape))
+
+
+def _check_det(J):
+    if not np.all(J > 0.0):
+        raise DomainError("det F <= 0 at %d voxel(s)" % int(np.sum(~(J > 0.0))))
+
+
+def nh_energy(F, mu, lam):
+    """Compressible neo-Hookean energy W = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2."""
+    J = np.linalg.det(F)
+    _check_det(J)
+    lnJ = np.log(J)
+    I1 = np.einsum("nij,nij->n", F, F)
+    return 0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ ** 2
+
+
+def nh_stress(F, mu, lam):
+    """First Piola-Kirchhoff stress P = dW/dF = mu (F - F^-T) + lam ln J F^-T."""
+    J = np.linalg.det(F)
+    _check_det(J)
+    FiT = np.linalg.inv(F).transpose(0, 2, 1)
+    lnJ = np.log(J)
+    return mu[:, None, None] * (F - FiT) + (lam * lnJ)[:, None, None] * FiT
+
+
+def nh_tangent_apply(F, mu, lam, dF):
+    """K : dF with K = dP/dF (eq. 4) for the neo-Hookean law.
+
+    dP = mu dF + lam tr(F^-1 dF) F^-T + (mu - lam ln J) F^-T dF^T F^-T.
+    """
+    J = np.linalg.det(F)
+    _check_det(J)
+    Finv = np.linalg.inv(F)
+    FiT = Finv.transpose(0, 2, 1)
+    lnJ = np.log(J)
+    tr = np.einsum("nij,nji->n", Finv, dF)
+    back = FiT @ dF.transpose(0, 2, 1) @ FiT
+    return (mu[:, None, None] * dF + (lam * tr)[:, None, None] * FiT
+            + (mu - lam * lnJ)[:, None, None] * back)
+
+
+def _green_lagrange(F):
+    return 0.5 * (F.transpose(0, 2, 1) @ F - np.eye(3))
+
+
+def svk_energy(F, C):
+    """Saint Venant-Kirchhoff energy W = 1/2 E : C : E, E = (F^T F - I)/2; C shape (M,3,3,3,3)."""
+    E = _green_lagrange(F)
+    return 0.5 * np.einsum("nij,nijkl,nkl->n", E, C, E)
+
+
+def svk_stress(F, C):
+    """P = F S with S = C : E (Saint Venant-Kirchhoff)."""
+    E = _green_lagrange(F)
+    S = np.einsum("nijkl,nkl->nij", C, E)
+    return F @ S
+
+
+def svk_tangent_apply(F, C, dF):
+    """K : dF = dF S + F (C : sym(F^T dF)) for Saint Venant-Kirchhoff."""
+    E = _green_lagrange(F)
+    S = np.einsum("nijkl,nkl->nij", C, E)
+    FtdF = F.transpose(0, 2, 1) @ dF
+    dE = 0.5 * (FtdF + FtdF.transpose(0, 2, 1))
+    dS = np.einsum("nijkl,nkl->nij", C, dE)
+    return dF @ S + F @ dS
+
+
+# --------------------------------------------------------------------------------------
+# The solver: Newton (eq. 4, 20) with conjugate gradients on G*(K : dF) (Sec. 2.2-2.3)
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class StepRecord:
+    """Outcome of one load increment."""
+    F_avg: np.ndarray
+    P_avg: np.ndarray
+    newton_iters: int
+    cg_iters: int
+    cg_per_newton: list = field(default_factory=list)
+    crit: float = float("nan")
+
+
+class Oracle:
+    """Plain FP64 Galerkin-FFT solver with per-component stress / deformation control.
+
+    Usage mirrors the C library: set the grid, the material, the control mask and the
+    load history, then call :meth:`step` once per increment.
+    """
+
+    CHUNK = 1 << 18  # voxels per material evaluation chunk (bounds temporary memory)
+
+    def __init__(self, shape, lengths=(1.0, 1.0, 1.0)):
+        self.shape = tuple(int(n) for n in shape)
+        self.lengths = tuple(float(L) for L in lengths)
+        self.N = int(np.prod(self.shape))
+        self.kind = None
+        self.phase = None
+        self.scale = np.ones(self.N)
+        self.mask = np.zeros(9)
+        self.target = None
+        self.newton_tol = 1e-6
+        self.cg_tol = 1e-8
+        self.cg_forcing = 0.0
+        self.max_newton = 50
+        self.max_cg = 5000
+        self.k = 0
+        self.cg_breakdowns = 0
+        self.F = np.tile(EYE9[:, None], (1, self.N)).reshape((9,) + self.shape)
+        self.history: list[StepRecord] = []
+
+    # ---- set-up ---------------------------------------------------------------------
+    def set_material_neohookean(self, phase, mu, lam):
+        self.kind = "nh"
+        self.phase = np.asarray(phase).reshape(-1).astype(np.int64)
+        self.mu_tab = np.asarray(mu, dtype=float).reshape(-1)
+        self.lam_tab = np.asarray(lam, dtype=float).reshape(-1)
+
+    def set_material_svk(self, phase, C):
+        """C: per-phase stiffness, shape (nphase, 3, 3, 3, 3) or (nphase, 81)."""
+        self.kind = "svk"
+        self.phase = np.asarray(phase).reshape(-1).astype(np.int64)
+        self.C_tab = np.asarray(C, dtype=float).reshape(-1, 3, 3, 3, 3)
+
+    def set_stiffness_scale(self, s):
+        """Per-voxel factor s(x) > 0 multiplying every modulus of the voxel's phase."""
+        self.scale = np.ones(self.N) if s is None else np.asarray(s, float).reshape(-1).copy()
+
+    def set_control(self, mask):
+        self.mask = np.asarray(mask, dtype=float).reshape(9).copy()
+
+    def set_history(self, target):
+        """target[k-1] holds, for increment k, P-bar on stress-controlled and F-bar on
+        deformation-controlled components (Sec. 2.3, eq. 21)."""
+        self.target = np.asarray(target, dtype=float).reshape(-1, 9).copy()
+
+    def set_tolerances(self, newton_tol, cg_tol, cg_forcing=0.0, max_newton=50, max_cg=5000):
+        self.newton_tol, self.cg_tol, self.cg_forcing = float(newton_tol), float(cg_tol), float(cg_forcing)
+        self.max_newton, self.max_cg = int(max_newton), int(max_cg)
+
+    def set_state(self, F9, k=None):
+        self.F = np.array(F9, dtype=float).reshape((9,) + self.shape)
+        if k is not None:
+            self.k = int(k)
+
+    # ---- material evaluation ---------------------------------------------------------
+    def _chunks(self):
+        for lo in range(0, self.N, self.CHUNK):
+            yield slice(lo, min(self.N, lo + self.CHUNK))
+
+    def _mat_args(self, sl):
+        ph = self.phase[sl]
+        s = self.scale[sl]
+        if self.kind == "nh":
+            return self.mu_tab[ph] * s, self.lam_tab[ph] * s
+        return (self.C_tab[ph] * s[:, None, None, None, None],)
+
+    def stress(self, F9=None) -> np.ndarray:
+        """P(F) at every voxel, (9, nx, ny, nz)."""
+        Fv = _voxels(self.F if F9 is None else F9)
+        out = np.empty_like(Fv)
+        for sl in self._chunks():
+            args = self._mat_args(sl)
+            out[sl] = nh_stress(Fv[sl], *args) if self.kind == "nh" else svk_stress(Fv[sl], *args)
+        return _field(out, self.shape)
+
+    def tangent_apply(self, dF9, F9=None) -> np.ndarray:
+        """K(F) : dF at every voxel (eq. 4)."""
+        Fv = _voxels(self.F if F9 is None else F9)
+        dv = _voxels(dF9)
+        out = np.empty_like(Fv)
+        for sl in self._chunks():
+            args = self._mat_args(sl)
+            if self.kind == "nh":
+                out[sl] = nh_tangent_apply(Fv[sl], *args, dv[sl])
+            else:
+                out[sl] = svk_tangent_apply(Fv[sl], *args, dv[sl])
+        return _field(out, self.shape)
+
+    # ---- linear algebra of one Newton iteration --------------------------------------
+    def apply_operator(self, v9, F9=None) -> np.ndarray:
+        """A(v) = G*(K : v), the left-hand side of eq. (20)."""
+        return apply_projection(self.tangent_apply(v9, F9), self.mask, self.lengths)
+
+    def residual(self, P9, Pbar9) -> np.ndarray:
+        """b = -G*(P(F) - P-bar), the right-hand side of eq. (20).
+
+        P-bar is uniform, so it only meets G* at xi = 0, where the mask keeps it on the
+        stress-controlled components and drops it on the deformation-controlled ones.
+        """
+        diff = P9 - np.asarray(Pbar9, float).reshape(9, 1, 1, 1)
+        return -apply_projection(diff, self.mask, self.lengths)
+
+    def rms(self, v9) -> float:
+        """Voxel-averaged L2 norm: sqrt( (1/N) sum_x |v(x)|^2 ) (Sec. 4)."""
+        return math.sqrt(float(np.vdot(v9, v9)) / self.N)
+
+    def conjugate_gradient(self, b9, F9=None):
+        """Solve A dF = b by plain conjugate gradients from dF = 0 (Sec. 2.1).
+
+        Stop when rms(r) <= max(cg_tol, cg_forcing * rms(b)) (absolute voxel-averaged L2
+        norm of the residual, Sec. 4).  Returns (dF, iterations).
+
+        Breakdown (p.Ap <= 0 or not finite): at the first iteration nothing can be done and
+        BreakdownError is raised; later, the iterate reached so far is returned and the
+        count ``self.cg_breakdowns`` is raised by one.  Under full stress control the rigid
+        rotations that leave P-bar unchanged make A singular (slightly indefinite away from
+        equilibrium); CG then stalls at round-off level and the Newton loop carries on.
+        """
+        x = np.zeros_like(b9)
+        r = b9.copy()
+        p = r.copy()
+        rr = float(np.vdot(r, r))
+        tol = max(self.cg_tol, self.cg_forcing * math.sqrt(rr / self.N))
+        it = 0
+        while math.sqrt(rr / self.N) > tol:
+            if it >= self.max_cg:
+                raise NotConvergedError("CG reached max_cg=%d" % self.max_cg)
+            Ap = self.apply_operator(p, F9)
+            pAp = float(np.vdot(p, Ap))
+            if not (pAp > 0.0 and math.isfinite(pAp)):
+                if it == 0 or not math.isfinite(pAp):
+                    raise BreakdownError("CG breakdown: p.Ap = %r at iteration %d" % (pAp, it))
+                self.cg_breakdowns += 1
+                break
+            alpha = rr / pAp
+            x += alpha * p
+            r -= alpha * Ap
+            rr_new = float(np.vdot(r, r))
+            beta = rr_new / rr
+            p = r + beta * p
+            rr = rr_new
+            it += 1
+        return x, it
+
+    def averages(self, F9=None, P9=None):
+        F9 = self.F if F9 is None else F9
+        P9 = self.stress(F9) if P9 is None else P9
+        return F9.reshape(9, -1).mean(axis=1), P9.reshape(9, -1).mean(axis=1)
+
+    # ---- one load increment ----------------------------------------------------------
+    def step(self) -> StepRecord:
+        """Advance one increment: shift the prescribed F means, then Newton (eq. 20/22)."""
+        if self.kind is None or self.target is None:
+            raise OracleError("material and history must be set before step()")
+        k = self.k + 1
+        if k > len(self.target):
+            raise OracleError("history exhausted")
+        fmask = self.mask == 0
+        prev = EYE9 if k == 1 else self.target[k - 2]
+        # deformation-controlled means move uniformly by the change of F-bar (eq. 3, 21)
+        shift = np.where(fmask, self.target[k - 1] - prev, 0.0)
+        Pbar = np.where(fmask, 0.0, self.target[k - 1])
+        self.F = self.F + shift.reshape(9, 1, 1, 1)
+        rec = self.newton(Pbar)
+        self.k = k
+        self.history.append(rec)
+        return rec
+
+    def target_stress(self, k=None):
+        """P-bar of increment k (default: the current one) on the stress-controlled
+        components, 0 elsewhere."""
+        k = self.k if k is None else k
+        return np.where(self.mask > 0, self.target[k - 1], 0.0)
+
+    def newton(self, Pbar) -> StepRecord:
+        """Newton iterations (eq. 4, 20) from the current F to equilibrium under P-bar.
+
+        Each iteration evaluates P(F) and b = -G*(P - P-bar), stops at once if
+        rms(b) <= cg_tol (nothing left to correct), else solves A dF = b by CG, sets
+        F += dF and stops when max_x |dF(x)| / |<F>| < newton_tol (Sec. 4).
+        """
+        newton = 0
+        cg_total = 0
+        per = []
+        crit = float("inf")
+        converged = False
+        for _ in range(self.max_newton):
+            newton += 1
+            P = self.stress()
+            b = self.residual(P, Pbar)
+            if self.rms(b) <= self.cg_tol:
+                per.append(0)
+                converged = True
+                break
+            dF, its = self.conjugate_gradient(b)
+            per.append(its)
+            cg_total += its
+            self.F = self.F + dF
+            Favg = self.F.reshape(9, -1).mean(axis=1)
+            crit = float(np.max(np.sqrt(np.sum(dF.reshape(9, -1) ** 2, axis=0)))) / float(np.linalg.norm(Favg))
+            if crit < self.newton_tol:
+                converged = True
+                break
+        if not converged:
+            raise NotConvergedError("Newton reached max_newton=%d (crit %.3e)" % (self.max_newton, crit))
+        Favg, Pavg = self.averages()
+        return StepRecord(Favg, Pavg, newton, cg_total, per, crit)
+
+    # ---- adjoint ---------------------------------------------------------------------
+    def adjoint_grad_scale(self, a9) -> np.ndarray:
+        """Gradient of J = a : <F> with respect to the per-voxel stiffness scale s(x).
+
+        At a converged state G*(P(F, s) - P-bar) = 0 with the unknown part of F in the
+        range of G*.  Differentiating, A dF/ds = -G*(dP/ds); J changes by
+        <a/N, dF> = <G*(a/N), dF>.  With lam solving A lam = G*(a/N) (A is symmetric on
+        the range of G*), dJ/ds(x) = -lam(x) : dP/ds(x) = -lam(x) : P(x) / s(x), because
+        every modulus is proportional to s.
+        """
+        g = np.broadcast_to(np.asarray(a9, float).reshape(9, 1, 1, 1) / self.N, (9,) + self.shape)
+        rhs = apply_projection(np.ascontiguousarray(g), self.mask, self.lengths)
+        lam, _ = self.conjugate_gradient(rhs)
+        P = self.stress()
+        return -(np.sum(lam * P, axis=0) / self.scale.reshape(self.shape))
+
+
+def run_history(oracle: Oracle, nsteps=None):
+    """Run increments 1..nsteps (default: the whole history); returns the records."""
+    n = len(oracle.target) if nsteps is None else int(nsteps)
+    return [oracle.step() for _ in range(n)]
