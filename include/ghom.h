@@ -1,0 +1,185 @@
+/*
+ * ghom.h -- C ABI of libghom.so: Galerkin-FFT homogenization with macroscopic stress,
+ * deformation-gradient or mixed control, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Lucarini, J. Segurado, "An algorithm for stress and mixed control in
+ * Galerkin based FFT homogenization", arXiv:1901.06531.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A tensor field is 9 contiguous planes of N = nx*ny*nz values (C order, z fastest):
+ *    value (c, x, y, z) sits at c*N + (x*ny + y)*nz + z, component c = 3*i + j holding the
+ *    tensor entry (i, j).  This is a NumPy array of shape (9, nx, ny, nz).
+ *  - Scalar per-voxel fields (phase, stiffness scale) are single planes of N values.
+ *  - A control mask is 9 bytes: mask[c] = 1 prescribes the macroscopic first
+ *    Piola-Kirchhoff stress component c (the paper's IJ terms, Sec. 2.3), mask[c] = 0
+ *    prescribes the macroscopic deformation-gradient component c (ij terms).
+ *  - Host pointers ("host") are read or written synchronously and stay owned by the
+ *    caller; the library copies what it keeps.  Device pointers ("dev") are HIP device
+ *    memory owned by the caller, accessed on the context's stream; the call returns after
+ *    the stream has finished with them.
+ *  - Every call returns GHOM_OK (0) or a negative status; it never throws.  The message
+ *    of the last failure of a context is returned by ghom_last_error.
+ *  - One context per host thread and stream.  All device memory of a context is
+ *    allocated by ghom_create and released by ghom_destroy.
+ */
+#ifndef GHOM_H
+#define GHOM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ghom_ctx ghom_ctx;
+
+/* Arithmetic of the conjugate-gradient solve.
+ *  GHOM_FP64       : everything in float64.
+ *  GHOM_FP32_SPLIT : CG vectors, tangent state and the transforms inside CG in float32
+ *                    with float64 dot products; F, P, the Newton residual, the averages
+ *                    and a float64 re-projection of every Newton correction in float64. */
+enum { GHOM_FP64 = 0, GHOM_FP32_SPLIT = 1 };
+
+enum {
+  GHOM_OK = 0,
+  GHOM_EINVAL = -1,         /* bad argument (message says which)                          */
+  GHOM_ENOMEM = -2,         /* device allocation failed                                    */
+  GHOM_EHIP = -3,           /* a HIP runtime call or kernel launch failed                  */
+  GHOM_ENOTCONVERGED = -4,  /* Newton or CG iteration cap; fields hold the last iterate    */
+  GHOM_ESINGULAR = -5,      /* CG breakdown at its first iteration (p.Ap <= 0)             */
+  GHOM_EDOMAIN = -6,        /* det F <= 0 at some voxel                                    */
+  GHOM_ESTATE = -7          /* call order: e.g. step before material, control or history   */
+};
+
+/* Fields readable with ghom_get_field / ghom_get_field_device. */
+enum { GHOM_FIELD_F = 0, GHOM_FIELD_P = 1 };
+
+/* Outcome of one load increment (ghom_step) or one Newton solve. */
+typedef struct {
+  int newton_iters;    /* Newton iterations (residual evaluations)                         */
+  int cg_iters_total;  /* conjugate-gradient iterations summed over the Newton iterations   */
+  int cg_breakdowns;   /* CG solves stopped early by p.Ap <= 0 after their first iteration */
+  int status;          /* the call's return value                                          */
+  double crit;         /* last Newton criterion max_x |dF(x)| / |<F>|                      */
+  double res_rms;      /* voxel-averaged L2 norm of the last Newton residual               */
+  double t_total_ms;   /* wall time of the call                                            */
+  double t_cg_ms;      /* time inside the CG loops                                         */
+} ghom_step_info;
+
+/* Creates a context for an nx x ny x nz voxel grid of the periodic cell of edge lengths
+ * (Lx, Ly, Lz) (the frequency vector is xi_d = k_d / L_d, Sec. 2.1 "Projection operator").
+ * Each n_d must be one of 4, 6, 8, 9, 12, 16, 18, 24, 27, 32, 36, 48, 64, 72, 96, 128, 144,
+ * 192, 256, 512.  precision: GHOM_FP64 or GHOM_FP32_SPLIT.  device: HIP device index.
+ * hip_stream: a hipStream_t to run on (e.g. torch's current stream), or NULL for a new
+ * stream owned by the context.  On success *out receives the context. */
+int ghom_create(ghom_ctx **out, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                int precision, int device, void *hip_stream);
+
+/* Releases the context and all its device memory (NULL is ignored). */
+void ghom_destroy(ghom_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char *ghom_last_error(const ghom_ctx *ctx);
+
+/* Compressible neo-Hookean phases: W = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,
+ * P = mu (F - F^-T) + lam ln J F^-T.  phase (host, N values < nphase), mu and lambda
+ * (host, nphase values each).  Resets the deformation to F = I and the increment to 0. */
+int ghom_set_material_neohookean(ghom_ctx *ctx, const uint16_t *phase, int nphase,
+                                 const double *mu, const double *lambda);
+
+/* Saint Venant-Kirchhoff phases (Sec. 3.1): P = F S, S = C : E, E = (F^T F - I)/2.
+ * C (host) holds nphase stiffness tensors of 81 values C_ijkl (index ((i*3+j)*3+k)*3+l),
+ * each with the minor and major symmetries (checked; EINVAL otherwise).
+ * Resets the deformation to F = I and the increment to 0. */
+int ghom_set_material_svk(ghom_ctx *ctx, const uint16_t *phase, int nphase, const double *C);
+
+/* Per-voxel stiffness scale s(x) > 0 multiplying every modulus of the voxel (host, N
+ * values; NULL restores s = 1).  Used by ghom_adjoint_grad_scale. */
+int ghom_set_stiffness_scale(ghom_ctx *ctx, const double *s);
+
+/* Control mask of eq. (22) (host, 9 bytes, see above). */
+int ghom_set_control(ghom_ctx *ctx, const uint8_t mask[9]);
+
+/* Load history (host, nsteps x 9): row k-1 holds, for increment k, the prescribed
+ * P-bar on stress-controlled and F-bar on deformation-controlled components (eq. 21).
+ * The deformation-controlled means are moved uniformly by the change of F-bar at each
+ * increment (F-bar of increment 0 is the identity). */
+int ghom_set_history(ghom_ctx *ctx, int nsteps, const double *target);
+
+/* Stopping rules (Sec. 4): CG stops when the voxel-averaged L2 norm of its residual,
+ * sqrt(sum |r|^2 / N), is <= max(cg_tol, cg_forcing * that norm of the right-hand side);
+ * Newton stops when max_x |dF(x)| / |<F>| < newton_tol, or when the residual itself is
+ * already <= cg_tol.  Defaults: 1e-6, 1e-8, 0, 50, 5000. */
+int ghom_set_tolerances(ghom_ctx *ctx, double newton_tol, double cg_tol, double cg_forcing,
+                        int max_newton, int max_cg);
+
+/* Advances one load increment: shifts the deformation-controlled means, then Newton
+ * (eq. 20) with CG on A(dF) = G*(K : dF) and the modified projection of eq. (22).
+ * info (nullable, host) receives the iteration counts and timings.  On
+ * GHOM_ENOTCONVERGED the fields hold the last iterate; on GHOM_ESINGULAR / GHOM_EDOMAIN
+ * the increment counter is not advanced. */
+int ghom_step(ghom_ctx *ctx, ghom_step_info *info);
+
+/* Re-solves equilibrium at the current increment without moving the prescribed means
+ * (e.g. after ghom_set_stiffness_scale or ghom_load_state).  info as in ghom_step. */
+int ghom_resolve(ghom_ctx *ctx, ghom_step_info *info);
+
+/* Voxel averages <F> and <P> of the current state (host, 9 values each, float64). */
+int ghom_get_averages(ghom_ctx *ctx, double Fbar[9], double Pbar[9]);
+
+/* Copies field `which` (GHOM_FIELD_F or GHOM_FIELD_P, float64, 9 x N) to host memory. */
+int ghom_get_field(ghom_ctx *ctx, int which, double *host_out);
+
+/* Same into caller-owned device memory (float64, 9 x N). */
+int ghom_get_field_device(ghom_ctx *ctx, int which, double *dev_out);
+
+/* Current deformation gradient (host, 9 x N) and increment index. */
+int ghom_save_state(ghom_ctx *ctx, double *F_out, int *step_out);
+
+/* Sets the deformation gradient (host, 9 x N) and the increment index (0..nsteps). */
+int ghom_load_state(ghom_ctx *ctx, const double *F_in, int step);
+
+/* Adjoint gradient of J = a : <F> with respect to s(x) at the current (converged) state:
+ * solves A lam = G*(a/N) with the same operator, then dJ/ds(x) = -lam(x) : P(x) / s(x).
+ * a (host, 9 values), grad_out (host, N values). */
+int ghom_adjoint_grad_scale(ghom_ctx *ctx, const double a[9], double *grad_out);
+
+/* ---- hot-path entry points on device memory ------------------------------------- */
+
+/* Av = A(v) = G*(K(F) : v) (eq. 20 left-hand side) at the current F.  v and Av are
+ * device arrays of 9 x N values of the CG type: float64 (GHOM_FP64) or float32
+ * (GHOM_FP32_SPLIT); they must not overlap. */
+int ghom_apply_operator(ghom_ctx *ctx, const void *v_dev, void *Av_dev);
+
+/* out = G*(in) (float64 device arrays of 9 x N; in may equal out): the modified
+ * projection of eq. (22) with the context's mask, applied through the 3-D transforms. */
+int ghom_apply_projection(ghom_ctx *ctx, const double *in_dev, double *out_dev);
+
+/* out = -G*(P(F) - P-bar) (float64 device array of 9 x N), the right-hand side of
+ * eq. (20) at the current F for the stress target Pbar (host, 9 values; only the
+ * stress-controlled components are used).  Also refreshes P and the tangent state. */
+int ghom_residual(ghom_ctx *ctx, const double Pbar[9], double *out_dev);
+
+/* ---- measurement ------------------------------------------------------------------ */
+
+/* Enables (1) or disables (0) HIP-event timing of every kernel launch of the context. */
+int ghom_set_profiling(ghom_ctx *ctx, int on);
+
+/* Kernel timing records: number of distinct kernel names seen since profiling started. */
+int ghom_profile_count(ghom_ctx *ctx);
+
+/* Name, launch count and total milliseconds of record i (0 <= i < ghom_profile_count).
+ * name_out receives at most name_cap bytes including the terminating zero.  Waits for
+ * the context's stream. */
+int ghom_profile_get(ghom_ctx *ctx, int i, char *name_out, int name_cap, int *launches,
+                     double *total_ms);
+
+/* Clears the timing records. */
+int ghom_profile_reset(ghom_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GHOM_H */

@@ -1,0 +1,801 @@
+// HIP kernels (gfx950) of the Galerkin-FFT Newton / conjugate-gradient solver with
+// stress and mixed control.
+//
+// Field layout: a tensor field is 9 planes of N = nx*ny*nz values, plane c = 3*i + j
+// holds entry (i, j); within a plane the voxel (x, y, z) sits at (x*ny + y)*nz + z.
+// Spectrum layout: after the real-to-complex transform along z only the wave numbers
+// kz in [0, nzh) are kept (nzh = nz/2 for even nz: the Nyquist plane is zeroed by the
+// projection, eq. 10; nzh = (nz+1)/2 for odd nz).  Plane c of the spectrum holds
+// Nh = nx*ny*nzh complex values at (x*ny + y)*nzh + kz; passes along y and x transform
+// in place, so after the x pass the entry (kx, ky, kz) sits at (kx*ny + ky)*nzh + kz.
+//
+// One application of the operator of eq. (20), A(v) = G*(K : v), is five passes:
+//   zfwd  : K : v per voxel (or a plain copy), real-to-complex along z
+//   yfwd  : complex transform along y
+//   xproj : transform along x, the projection G* of eq. (22) at each frequency,
+//           inverse transform along x
+//   yinv  : inverse along y
+//   zinv  : complex-to-real along z, fused dot products for CG
+#pragma once
+
+#include <cstdint>
+
+#include "dft.hpp"
+
+namespace ghom {
+
+struct Geo {
+  int nx, ny, nz, nzh;
+  long long N;    // voxels
+  long long Nh;   // spectrum points per component
+  double invL[3];
+};
+
+enum { MAT_NH = 1, MAT_SVK = 2 };
+constexpr int kNHState = 12;   // F^-T (9), a = s mu, b = s lam, c = s (mu - lam ln J)
+constexpr int kSVKState = 16;  // F (9), S in Voigt order 11 22 33 23 13 12 (6), s (1)
+
+// scalars shared by the CG kernels (device memory)
+struct CGScalars {
+  double rr;       // r.r of the current iterate
+  double pAp;
+  double alpha;
+  double beta;
+  double thresh;   // stop when rr <= thresh (= tol^2 N)
+  int it;          // iterations done
+  int max_it;
+  int done;        // 1: stop (converged, breakdown or cap)
+  int status;      // 0 running, 1 converged, 2 breakdown, 3 iteration cap
+};
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Deterministic block sum (fixed order): valid in thread 0 only.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  constexpr int NW = (NT + 63) / 64;
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) s += sh[i];
+  }
+  __syncthreads();
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  constexpr int NW = (NT + 63) / 64;
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) s = fmax(s, sh[i]);
+  }
+  __syncthreads();
+  return s;
+}
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+
+// LDS budget per workgroup, in complex values
+template <typename T> constexpr int lds_cx() { return sizeof(T) == 8 ? 4096 : 8192; }
+
+// column passes: A threads per line, TC lines per workgroup
+template <typename T, int A, int B> struct ColCfg {
+  static constexpr int N = A * B;
+  static constexpr int TC = pow2_floor(cmax(1, cmin(64, cmin(256 / A, lds_cx<T>() / N))));
+  static constexpr int NT = A * TC;
+};
+// z passes: LP pairs of real lines (9 components each) per workgroup
+template <typename T, int A, int B> struct ZCfg {
+  static constexpr int N = A * B;
+  static constexpr int LP = cmax(1, cmin(256 / (9 * A), lds_cx<T>() / (9 * N)));
+  static constexpr int NT = 9 * LP * A;
+};
+
+// ---------------------------------------------------------------------------------
+// four-step building blocks (n = A*B; thread q in [0, A) of a line)
+// ---------------------------------------------------------------------------------
+// Forward half: v[b] = x[q + A b] (b < B)  ->  v[c] = W_n^(q c) * DFT_B(v)[c]
+template <int A, int B, int DIR, typename T>
+__device__ __forceinline__ void four_step_first(cx<T>* v, int q, const cx<T>* __restrict__ tw) {
+  dft<B, DIR>(v);
+#pragma unroll
+  for (int c = 1; c < B; ++c) {
+    const cx<T> w = tw[q * c];
+    v[c] = DIR < 0 ? cmul(v[c], w) : cmulc(v[c], w);
+  }
+}
+
+// second half, reading the exchanged values: thread q owns c = q + A i (i < B/A);
+// for each, t[a] = Y[a][c] (a < A) -> DFT_A -> X[c + B d], stored in v[i + (B/A) d]
+// (so v[e] = X[q + A e]).  'get(c, a)' returns Y[a][c].
+template <int A, int B, int DIR, typename T, typename Get>
+__device__ __forceinline__ void four_step_second(cx<T>* v, int q, Get&& get) {
+  constexpr int R = B / A;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int c = q + A * i;
+    cx<T> t[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) t[a] = get(c, a);
+    dft<A, DIR>(t);
+#pragma unroll
+    for (int d = 0; d < A; ++d) v[i + R * d] = t[d];
+  }
+}
+
+// inverse of the second half for data held as v[e] = X[q + A e]: for each c = q + A i,
+// DFT_A^(DIR) over d of X[c + B d], twiddle by W_n^(-DIR... ) and hand Z[c][a] to put(c, a, z)
+template <int A, int B, int DIR, typename T, typename Put>
+__device__ __forceinline__ void four_step_second_inv(const cx<T>* v, int q, const cx<T>* __restrict__ tw,
+                                                     Put&& put) {
+  constexpr int R = B / A;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int c = q + A * i;
+    cx<T> t[A];
+#pragma unroll
+    for (int d = 0; d < A; ++d) t[d] = v[i + R * d];
+    dft<A, DIR>(t);
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const cx<T> w = tw[a * c];
+      put(c, a, DIR < 0 ? cmul(t[a], w) : cmulc(t[a], w));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// y pass: in-place complex transform along y of every spectrum line (c, x, kz)
+// ---------------------------------------------------------------------------------
+template <typename T, int A, int B, int DIR>
+__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
+ypass_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const CGScalars* __restrict__ sc) {
+  using Cfg = ColCfg<T, A, B>;
+  constexpr int TC = Cfg::TC;
+  __shared__ cx<T> lds[A * B * TC];
+  if (sc && sc->done) return;
+  const int j = threadIdx.x % TC;
+  const int q = threadIdx.x / TC;
+  const long long ncols = 9LL * g.nx * g.nzh;
+  const long long col = (long long)blockIdx.x * TC + j;
+  const bool ok = col < ncols;
+  const long long grp = col / g.nzh;  // (c, x)
+  const long long base = grp * ((long long)g.ny * g.nzh) + (col - grp * g.nzh);
+  const long long rs = g.nzh;
+  cx<T> v[B];
+#pragma unroll
+  for (int e = 0; e < B; ++e) v[e] = ok ? H[base + (long long)(q + A * e) * rs] : cx<T>{0, 0};
+  four_step_first<A, B, DIR>(v, q, tw);
+#pragma unroll
+  for (int c = 0; c < B; ++c) lds[(c * A + q) * TC + j] = v[c];
+  __syncthreads();
+  four_step_second<A, B, DIR>(v, q, [&](int c, int a) { return lds[(c * A + a) * TC + j]; });
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < B; ++e) H[base + (long long)(q + A * e) * rs] = v[e];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// x pass with the modified projection (eq. 22), for one tensor row per blockIdx.y
+// ---------------------------------------------------------------------------------
+struct ProjParams {
+  unsigned mask;      // bit c set: component c is stress-controlled (IJ)
+  double post;        // output factor (scale / N: fixes the unnormalized transforms)
+  double off[9];      // value subtracted at xi = 0 on stress-controlled components
+};
+
+__device__ __forceinline__ int signed_k(int k, int n) { return k <= (n - 1) / 2 ? k : k - n; }
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
+xproj_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
+             const CGScalars* __restrict__ sc) {
+  using Cfg = ColCfg<T, A, B>;
+  constexpr int TC = Cfg::TC;
+  __shared__ cx<T> lds[A * B * TC];
+  if (sc && sc->done) return;
+  const int j = threadIdx.x % TC;
+  const int q = threadIdx.x / TC;
+  const int row = blockIdx.y;  // tensor row i: components 3i, 3i+1, 3i+2
+  const long long ncols = (long long)g.ny * g.nzh;
+  const long long col = (long long)blockIdx.x * TC + j;
+  const bool ok = col < ncols;
+  const long long rs = ncols;
+  cx<T> v[3][B];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + col;
+#pragma unroll
+    for (int e = 0; e < B; ++e) v[l][e] = ok ? src[(long long)(q + A * e) * rs] : cx<T>{0, 0};
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    four_step_first<A, B, -1>(v[l], q, tw);
+    if (l) __syncthreads();
+#pragma unroll
+    for (int c = 0; c < B; ++c) lds[(c * A + q) * TC + j] = v[l][c];
+    __syncthreads();
+    four_step_second<A, B, -1>(v[l], q, [&](int c, int a) { return lds[(c * A + a) * TC + j]; });
+  }
+  // projection at each frequency held by this thread: kx = q + A e
+  {
+    const int ky = ok ? (int)(col / g.nzh) : 0;
+    const int kz = ok ? (int)(col - (long long)ky * g.nzh) : 0;
+    const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
+    const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
+    const T xz = (T)(kz * g.invL[2]);
+    const T post = (T)pp.post;
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int kx = q + A * e;
+      const bool nyq = nyq_yz || ((g.nx % 2 == 0) && kx == g.nx / 2);
+      const T xx = (T)(signed_k(kx, g.nx) * g.invL[0]);
+      const T xi2 = xx * xx + xy * xy + xz * xz;
+      if (nyq) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) v[l][e] = cx<T>{0, 0};
+      } else if (kx == 0 && ky == 0 && kz == 0) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const int c = 3 * row + l;
+          if ((pp.mask >> c) & 1u) {
+            v[l][e].re = (v[l][e].re - (T)pp.off[c]) * post;
+            v[l][e].im = v[l][e].im * post;
+          } else {
+            v[l][e] = cx<T>{0, 0};
+          }
+        }
+      } else {
+        const T inv = post / xi2;
+        const cx<T> s = (v[0][e] * xx + v[1][e] * xy + v[2][e] * xz) * inv;
+        v[0][e] = s * xx;
+        v[1][e] = s * xy;
+        v[2][e] = s * xz;
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    __syncthreads();
+    four_step_second_inv<A, B, +1>(v[l], q, tw, [&](int c, int a, cx<T> z) { lds[(c * A + a) * TC + j] = z; });
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[l][b] = lds[(b * A + q) * TC + j];
+    dft<B, +1>(v[l]);
+  }
+  if (ok) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + col;
+#pragma unroll
+      for (int e = 0; e < B; ++e) dst[(long long)(q + A * e) * rs] = v[l][e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// pointwise tangents K : dF
+// ---------------------------------------------------------------------------------
+// neo-Hookean: K:dF = a dF + b (G:dF) G + c G dF^T G with G = F^-T
+template <typename T>
+__device__ __forceinline__ void tangent_nh(const T* st, const T* d, T* out) {
+  const T* G = st;
+  const T a = st[9], b = st[10], c = st[11];
+  T tr = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) tr += G[k] * d[k];
+  // M = dF^T G : M_kj = sum_l dF_lk G_lj
+  T M[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) M[3 * k + jj] = d[k] * G[jj] + d[3 + k] * G[3 + jj] + d[6 + k] * G[6 + jj];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      const T gm = G[3 * i] * M[jj] + G[3 * i + 1] * M[3 + jj] + G[3 * i + 2] * M[6 + jj];
+      out[3 * i + jj] = a * d[3 * i + jj] + b * tr * G[3 * i + jj] + c * gm;
+    }
+}
+
+// Saint Venant-Kirchhoff: K:dF = dF S + F (s C : sym(F^T dF)), C in 6x6 Voigt form
+template <typename T>
+__device__ __forceinline__ void tangent_svk(const T* st, const double* __restrict__ C6, const T* d, T* out) {
+  const T* F = st;
+  const T* S = st + 9;  // 11 22 33 23 13 12
+  const T s = st[15];
+  T E[6];
+  // (F^T dF)_ij = sum_k F_ki dF_kj ; dE = sym
+  auto ftd = [&](int i, int jj) { return F[i] * d[jj] + F[3 + i] * d[3 + jj] + F[6 + i] * d[6 + jj]; };
+  E[0] = ftd(0, 0);
+  E[1] = ftd(1, 1);
+  E[2] = ftd(2, 2);
+  E[3] = ftd(1, 2) + ftd(2, 1);  // engineering shear 2 dE23
+  E[4] = ftd(0, 2) + ftd(2, 0);
+  E[5] = ftd(0, 1) + ftd(1, 0);
+  T dS[6];
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    T acc = 0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) acc += (T)C6[6 * I + J] * E[J];
+    dS[I] = s * acc;
+  }
+  const T Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
+  const T dSm[9] = {dS[0], dS[5], dS[4], dS[5], dS[1], dS[3], dS[4], dS[3], dS[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += d[3 * i + k] * Sm[3 * k + jj] + F[3 * i + k] * dSm[3 * k + jj];
+      out[3 * i + jj] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// z forward pass: per voxel input (plain copy or K : p), real-to-complex along z
+// ---------------------------------------------------------------------------------
+enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2 };
+
+template <typename T, typename TIN>
+struct ZfwdArgs {
+  const TIN* in;              // Z_PLAIN: field to transform (9 planes)
+  T* p;                       // Z_NH/Z_SVK: CG direction (updated in place when beta != 0)
+  const T* r;                 // CG residual for p <- r + beta p
+  int update_p;               // nonzero: p <- r + beta p before use
+  const T* state;             // tangent state planes
+  const uint16_t* phase;      // SVK: phase of each voxel
+  const double* C6;           // SVK: per-phase 6x6 Voigt stiffness
+  cx<T>* H;                   // spectrum out
+  const cx<T>* tw;            // z twiddles
+  const CGScalars* sc;        // early exit / beta (nullable)
+};
+
+template <typename T, int A, int B, int MODE, typename TIN>
+__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
+zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
+  using Cfg = ZCfg<T, A, B>;
+  constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B;
+  __shared__ cx<T> lds[9 * LP * NZ];
+  if (args.sc && args.sc->done) return;
+  const long long nlines = (long long)g.nx * g.ny;
+  const long long line0 = (long long)blockIdx.x * (2 * LP);
+  T* ldsr = reinterpret_cast<T*>(lds);
+  const T beta = (MODE != Z_PLAIN && args.update_p) ? (T)args.sc->beta : (T)0;
+  // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
+  for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
+    const int lp = t / NZ, z = t - lp * NZ;
+    const long long line = line0 + lp;
+    T val[9];
+    if (line < nlines) {
+      const long long vox = line * NZ + z;
+      if constexpr (MODE == Z_PLAIN) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) val[c] = (T)args.in[c * g.N + vox];
+      } else {
+        T d[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) d[c] = args.p[c * g.N + vox];
+        if (args.update_p) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            d[c] = args.r[c * g.N + vox] + beta * d[c];
+            args.p[c * g.N + vox] = d[c];
+          }
+        }
+        if constexpr (MODE == Z_NH) {
+          T st[kNHState];
+#pragma unroll
+          for (int k = 0; k < kNHState; ++k) st[k] = args.state[k * g.N + vox];
+          tangent_nh(st, d, val);
+        } else {
+          T st[kSVKState];
+#pragma unroll
+          for (int k = 0; k < kSVKState; ++k) st[k] = args.state[k * g.N + vox];
+          tangent_svk(st, args.C6 + 36 * args.phase[vox], d, val);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) val[c] = 0;
+    }
+    const int pair = lp >> 1, part = lp & 1;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * NZ + z) + part] = val[c];
+  }
+  __syncthreads();
+  // phase 2: 9*LP complex transforms of length NZ (A threads each)
+  const int f = threadIdx.x / A, q = threadIdx.x - (threadIdx.x / A) * A;
+  cx<T>* L = lds + f * NZ;
+  cx<T> v[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) v[b] = L[q + A * b];
+  four_step_first<A, B, -1>(v, q, args.tw);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < B; ++c) L[c * A + q] = v[c];
+  __syncthreads();
+  four_step_second<A, B, -1>(v, q, [&](int c, int a) { return L[c * A + a]; });
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < B; ++e) L[q + A * e] = v[e];
+  __syncthreads();
+  // phase 3: split the two real lines' spectra, store kz < nzh
+  const int nzh = g.nzh;
+  for (int t = threadIdx.x; t < 9 * LP * nzh; t += NT) {
+    const int ff = t / nzh, kz = t - ff * nzh;
+    const int c = ff / LP, pair = ff - c * LP;
+    const cx<T> Zk = lds[ff * NZ + kz];
+    const cx<T> Zm = conj(lds[ff * NZ + (kz == 0 ? 0 : NZ - kz)]);
+    const cx<T> Ak = (Zk + Zm) * (T)0.5;
+    const cx<T> Bk = mul_i<-1>(Zk - Zm) * (T)0.5;
+    const long long l0 = line0 + 2 * pair;
+    if (l0 < nlines) args.H[c * g.Nh + l0 * nzh + kz] = Ak;
+    if (l0 + 1 < nlines) args.H[c * g.Nh + (l0 + 1) * nzh + kz] = Bk;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// z inverse pass: complex-to-real along z, write the field, fused partial dot products
+// ---------------------------------------------------------------------------------
+template <typename T, typename TOUT>
+struct ZinvArgs {
+  const cx<T>* H;
+  TOUT* out;                  // 9 planes
+  const TOUT* dot_with;       // nullable: partial sum of out . dot_with per block
+  double* partials;           // one value per block when dot_with != nullptr
+  const cx<T>* tw;
+  const CGScalars* sc;        // early exit (nullable)
+};
+
+template <typename T, int A, int B, typename TOUT>
+__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
+zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
+  using Cfg = ZCfg<T, A, B>;
+  constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B;
+  __shared__ cx<T> lds[9 * LP * NZ];
+  __shared__ double red[(NT + 63) / 64];
+  if (args.sc && args.sc->done) return;
+  const long long nlines = (long long)g.nx * g.ny;
+  const long long line0 = (long long)blockIdx.x * (2 * LP);
+  const int nzh = g.nzh;
+  // phase 1: Z[k] = A[k] + i B[k] with Hermitian completion; Nyquist (even NZ) is zero
+  for (int t = threadIdx.x; t < 9 * LP * nzh; t += NT) {
+    const int ff = t / nzh, kz = t - ff * nzh;
+    const int c = ff / LP, pair = ff - c * LP;
+    const long long l0 = line0 + 2 * pair;
+    const cx<T> a = l0 < nlines ? args.H[c * g.Nh + l0 * nzh + kz] : cx<T>{0, 0};
+    const cx<T> b = l0 + 1 < nlines ? args.H[c * g.Nh + (l0 + 1) * nzh + kz] : cx<T>{0, 0};
+    lds[ff * NZ + kz] = a + mul_i<+1>(b);
+    if (kz > 0) lds[ff * NZ + NZ - kz] = conj(a) + mul_i<+1>(conj(b));
+    if ((NZ % 2 == 0) && kz == 0) lds[ff * NZ + NZ / 2] = cx<T>{0, 0};
+  }
+  __syncthreads();
+  const int f = threadIdx.x / A, q = threadIdx.x - (threadIdx.x / A) * A;
+  cx<T>* L = lds + f * NZ;
+  cx<T> v[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) v[b] = L[q + A * b];
+  four_step_first<A, B, +1>(v, q, args.tw);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < B; ++c) L[c * A + q] = v[c];
+  __syncthreads();
+  four_step_second<A, B, +1>(v, q, [&](int c, int a) { return L[c * A + a]; });
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < B; ++e) L[q + A * e] = v[e];
+  __syncthreads();
+  // phase 3: real lines out
+  const T* ldsr = reinterpret_cast<const T*>(lds);
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
+    const int lp = t / NZ, z = t - lp * NZ;
+    const long long line = line0 + lp;
+    if (line >= nlines) continue;
+    const long long vox = line * NZ + z;
+    const int pair = lp >> 1, part = lp & 1;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * NZ + z) + part];
+      args.out[c * g.N + vox] = o;
+      if (args.dot_with) acc += (double)o * (double)args.dot_with[c * g.N + vox];
+    }
+  }
+  if (args.dot_with) {
+    const double s = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) args.partials[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// constitutive update (FP64): P(F), tangent state, partial sums of F and P
+// ---------------------------------------------------------------------------------
+constexpr int kVoxThreads = 256;
+
+template <typename TS, int KIND>
+__global__ void __launch_bounds__(kVoxThreads)
+constitutive_kernel(Geo g, const double* __restrict__ F, double* __restrict__ P, TS* __restrict__ state,
+                    const uint16_t* __restrict__ phase, const double* __restrict__ scale,
+                    const double* __restrict__ mat, double* __restrict__ partials, int* __restrict__ flag) {
+  __shared__ double red[kVoxThreads / 64];
+  double sums[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) sums[k] = 0.0;
+  int bad = 0;
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < g.N;
+       v += (long long)gridDim.x * kVoxThreads) {
+    double f[9], p[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) f[c] = F[c * g.N + v];
+    const int ph = phase[v];
+    const double s = scale ? scale[v] : 1.0;
+    const double cf0 = f[4] * f[8] - f[5] * f[7];
+    const double cf1 = f[5] * f[6] - f[3] * f[8];
+    const double cf2 = f[3] * f[7] - f[4] * f[6];
+    const double J = f[0] * cf0 + f[1] * cf1 + f[2] * cf2;
+    if (!(J > 0.0)) bad = 1;
+    if constexpr (KIND == MAT_NH) {
+      const double mu = s * mat[2 * ph], lam = s * mat[2 * ph + 1];
+      // G = F^-T = cofactor(F) / J
+      const double iJ = 1.0 / J;
+      double G[9];
+      G[0] = cf0 * iJ;
+      G[1] = cf1 * iJ;
+      G[2] = cf2 * iJ;
+      G[3] = (f[2] * f[7] - f[1] * f[8]) * iJ;
+      G[4] = (f[0] * f[8] - f[2] * f[6]) * iJ;
+      G[5] = (f[1] * f[6] - f[0] * f[7]) * iJ;
+      G[6] = (f[1] * f[5] - f[2] * f[4]) * iJ;
+      G[7] = (f[2] * f[3] - f[0] * f[5]) * iJ;
+      G[8] = (f[0] * f[4] - f[1] * f[3]) * iJ;
+      const double lnJ = J > 0.0 ? log(J) : 0.0;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p[c] = mu * (f[c] - G[c]) + lam * lnJ * G[c];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)G[c];
+      state[9 * g.N + v] = (TS)mu;
+      state[10 * g.N + v] = (TS)lam;
+      state[11 * g.N + v] = (TS)(mu - lam * lnJ);
+    } else {
+      const double* C6 = mat + 36 * ph;
+      // E = (F^T F - I)/2 in Voigt with engineering shears
+      auto ftf = [&](int i, int j) { return f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j]; };
+      double E[6];
+      E[0] = 0.5 * (ftf(0, 0) - 1.0);
+      E[1] = 0.5 * (ftf(1, 1) - 1.0);
+      E[2] = 0.5 * (ftf(2, 2) - 1.0);
+      E[3] = ftf(1, 2);
+      E[4] = ftf(0, 2);
+      E[5] = ftf(0, 1);
+      double S[6];
+#pragma unroll
+      for (int I = 0; I < 6; ++I) {
+        double acc = 0.0;
+#pragma unroll
+        for (int J2 = 0; J2 < 6; ++J2) acc += C6[6 * I + J2] * E[J2];
+        S[I] = s * acc;
+      }
+      const double Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          p[3 * i + j] = f[3 * i] * Sm[j] + f[3 * i + 1] * Sm[3 + j] + f[3 * i + 2] * Sm[6 + j];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)f[c];
+#pragma unroll
+      for (int I = 0; I < 6; ++I) state[(9 + I) * g.N + v] = (TS)S[I];
+      state[15 * g.N + v] = (TS)s;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      P[c * g.N + v] = p[c];
+      sums[c] += f[c];
+      sums[9 + c] += p[c];
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    const double s = block_sum<kVoxThreads>(sums[k], red);
+    if (threadIdx.x == 0) partials[(long long)blockIdx.x * 18 + k] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// CG vector kernels
+// ---------------------------------------------------------------------------------
+// x = 0, r = (T) b, p = r, partial r.r
+template <typename T>
+__global__ void __launch_bounds__(kVoxThreads)
+cg_init_kernel(long long n, const double* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
+               T* __restrict__ p, double* __restrict__ partials) {
+  __shared__ double red[kVoxThreads / 64];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kVoxThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVoxThreads) {
+    const T v = (T)b[i];
+    x[i] = (T)0;
+    r[i] = v;
+    p[i] = v;
+    acc += (double)v * (double)v;
+  }
+  const double s = block_sum<kVoxThreads>(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha Ap, partial r.r
+template <typename T>
+__global__ void __launch_bounds__(kVoxThreads)
+cg_update_kernel(long long n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                 const T* __restrict__ Ap, const CGScalars* __restrict__ sc, double* __restrict__ partials) {
+  __shared__ double red[kVoxThreads / 64];
+  if (sc->done) return;
+  const T alpha = (T)sc->alpha;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kVoxThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVoxThreads) {
+    x[i] += alpha * p[i];
+    const T rn = r[i] - alpha * Ap[i];
+    r[i] = rn;
+    acc += (double)rn * (double)rn;
+  }
+  const double s = block_sum<kVoxThreads>(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// sum of nparts partials in a fixed order, by one block
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ partials, int nparts, int stride,
+                                                  int k, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kRedThreads) acc += partials[(long long)i * stride + k];
+  return block_sum<kRedThreads>(acc, red);
+}
+
+// which: 0 = start (rr from partials, converged test), 1 = alpha (pAp), 2 = beta (rr_new)
+__global__ void __launch_bounds__(kRedThreads)
+cg_scalar_kernel(CGScalars* sc, const double* __restrict__ partials, int nparts, int which) {
+  __shared__ double red[kRedThreads / 64];
+  if (which != 0 && sc->done) return;
+  const double s = reduce_partials(partials, nparts, 1, 0, red);
+  if (threadIdx.x != 0) return;
+  if (which == 0) {
+    sc->rr = s;
+    sc->it = 0;
+    sc->done = 0;
+    sc->status = 0;
+    if (s <= sc->thresh) {
+      sc->done = 1;
+      sc->status = 1;
+    }
+  } else if (which == 1) {
+    sc->pAp = s;
+    if (!(s > 0.0) || !isfinite(s)) {
+      sc->done = 1;
+      sc->status = 2;
+    } else {
+      sc->alpha = sc->rr / s;
+    }
+  } else {
+    sc->beta = s / sc->rr;
+    sc->rr = s;
+    sc->it += 1;
+    if (s <= sc->thresh) {
+      sc->done = 1;
+      sc->status = 1;
+    } else if (sc->it >= sc->max_it) {
+      sc->done = 1;
+      sc->status = 3;
+    }
+  }
+}
+
+// column sums of a (nparts x K) partials table into out[0..K); the first nmax columns
+// are reduced with max instead of sum (one block, fixed order)
+__global__ void __launch_bounds__(kRedThreads)
+sum_columns_kernel(const double* __restrict__ partials, int nparts, int K, int nmax, double* __restrict__ out) {
+  __shared__ double red[kRedThreads / 64];
+  for (int k = 0; k < K; ++k) {
+    double r;
+    if (k < nmax) {
+      double acc = 0.0;
+      for (int i = threadIdx.x; i < nparts; i += kRedThreads) acc = fmax(acc, partials[(long long)i * K + k]);
+      r = block_max<kRedThreads>(acc, red);
+    } else {
+      r = reduce_partials(partials, nparts, K, k, red);
+    }
+    if (threadIdx.x == 0) out[k] = r;
+  }
+}
+
+// F += dF; partials: max |dF(x)|^2 and sums of F (10 columns)
+template <typename TD>
+__global__ void __launch_bounds__(kVoxThreads)
+newton_update_kernel(Geo g, double* __restrict__ F, const TD* __restrict__ dF, double* __restrict__ partials) {
+  __shared__ double red[kVoxThreads / 64];
+  double mx = 0.0;
+  double sums[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) sums[c] = 0.0;
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < g.N; v += (long long)gridDim.x * kVoxThreads) {
+    double n2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const double d = (double)dF[c * g.N + v];
+      const double fn = F[c * g.N + v] + d;
+      F[c * g.N + v] = fn;
+      n2 += d * d;
+      sums[c] += fn;
+    }
+    mx = fmax(mx, n2);
+  }
+  const double m = block_max<kVoxThreads>(mx, red);
+  if (threadIdx.x == 0) partials[(long long)blockIdx.x * 10] = m;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const double s = block_sum<kVoxThreads>(sums[c], red);
+    if (threadIdx.x == 0) partials[(long long)blockIdx.x * 10 + 1 + c] = s;
+  }
+}
+
+struct Shift9 { double d[9]; };
+
+__global__ void __launch_bounds__(kVoxThreads)
+shift_kernel(long long N, double* __restrict__ F, Shift9 s) {
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+      if (s.d[c] != 0.0) F[c * N + v] += s.d[c];
+  }
+}
+
+// uniform field value[c] in every voxel (FP64)
+__global__ void __launch_bounds__(kVoxThreads)
+fill9_kernel(long long N, double* __restrict__ out, Shift9 val) {
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) out[c * N + v] = val.d[c];
+  }
+}
+
+// dJ/ds(x) = -(lam(x) : P(x)) / s(x), lam the adjoint field (already divided by N)
+template <typename TL>
+__global__ void __launch_bounds__(kVoxThreads)
+adjoint_grad_kernel(long long N, const TL* __restrict__ lam, const double* __restrict__ P,
+                    const double* __restrict__ scale, double inv_n, double* __restrict__ grad) {
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc += (double)lam[c * N + v] * P[c * N + v];
+    grad[v] = -acc * inv_n / (scale ? scale[v] : 1.0);
+  }
+}
+
+}  // namespace ghom

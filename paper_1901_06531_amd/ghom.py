@@ -1,0 +1,272 @@
+"""ctypes binding of libghom.so (include/ghom.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module converts NumPy
+arrays to the C layouts, hands device pointers of torch tensors through, and turns status
+codes into exceptions.  Importing it loads the library and raises if it is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libghom.so")
+
+FP64 = 0
+FP32_SPLIT = 1
+FIELD_F = 0
+FIELD_P = 1
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
+          -6: "EDOMAIN", -7: "ESTATE"}
+
+
+class GhomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+        self.name = STATUS.get(code, "?")
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int), ("cg_iters_total", ctypes.c_int),
+                ("cg_breakdowns", ctypes.c_int), ("status", ctypes.c_int),
+                ("crit", ctypes.c_double), ("res_rms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("t_cg_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "ghom_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _d, _d, _d, _i, _i, _vp]),
+    "ghom_destroy": (None, [_vp]),
+    "ghom_last_error": (ctypes.c_char_p, [_vp]),
+    "ghom_set_material_neohookean": (_i, [_vp, _vp, _i, _vp, _vp]),
+    "ghom_set_material_svk": (_i, [_vp, _vp, _i, _vp]),
+    "ghom_set_stiffness_scale": (_i, [_vp, _vp]),
+    "ghom_set_control": (_i, [_vp, _vp]),
+    "ghom_set_history": (_i, [_vp, _i, _vp]),
+    "ghom_set_tolerances": (_i, [_vp, _d, _d, _d, _i, _i]),
+    "ghom_step": (_i, [_vp, ctypes.POINTER(StepInfo)]),
+    "ghom_resolve": (_i, [_vp, ctypes.POINTER(StepInfo)]),
+    "ghom_get_averages": (_i, [_vp, _vp, _vp]),
+    "ghom_get_field": (_i, [_vp, _i, _vp]),
+    "ghom_get_field_device": (_i, [_vp, _i, _vp]),
+    "ghom_save_state": (_i, [_vp, _vp, ctypes.POINTER(_i)]),
+    "ghom_load_state": (_i, [_vp, _vp, _i]),
+    "ghom_adjoint_grad_scale": (_i, [_vp, _vp, _vp]),
+    "ghom_apply_operator": (_i, [_vp, _vp, _vp]),
+    "ghom_apply_projection": (_i, [_vp, _vp, _vp]),
+    "ghom_residual": (_i, [_vp, _vp, _vp]),
+    "ghom_set_profiling": (_i, [_vp, _i]),
+    "ghom_profile_count": (_i, [_vp]),
+    "ghom_profile_get": (_i, [_vp, _i, ctypes.c_char_p, _i, ctypes.POINTER(_i), _dp]),
+    "ghom_profile_reset": (_i, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libghom.so not built at %s: run paper_1901_06531_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_ptr(t):
+    """Device pointer of a contiguous torch CUDA tensor."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _torch_sync():
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+
+
+class Solver:
+    """One Galerkin-FFT problem on one GPU (a ghom_ctx)."""
+
+    def __init__(self, shape, lengths=(1.0, 1.0, 1.0), precision=FP64, device=0, stream=None):
+        self.shape = tuple(int(n) for n in shape)
+        self.N = int(np.prod(self.shape))
+        self.precision = precision
+        self._c = ctypes.c_void_p()
+        rc = lib().ghom_create(ctypes.byref(self._c), *self.shape, *[float(v) for v in lengths],
+                               int(precision), int(device), stream)
+        if rc != 0:
+            raise GhomError(rc, "ghom_create failed for shape %s" % (self.shape,))
+
+    # -- plumbing ------------------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise GhomError(rc, lib().ghom_last_error(self._c).decode())
+        return rc
+
+    def close(self):
+        if self._c:
+            lib().ghom_destroy(self._c)
+            self._c = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- set-up --------------------------------------------------------------------------
+    def set_material_neohookean(self, phase, mu, lam):
+        ph = np.ascontiguousarray(np.asarray(phase).reshape(-1), dtype=np.uint16)
+        mu = np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)
+        lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(-1)
+        self._check(lib().ghom_set_material_neohookean(self._c, _ptr(ph), len(mu), _ptr(mu), _ptr(lam)))
+
+    def set_material_svk(self, phase, C):
+        ph = np.ascontiguousarray(np.asarray(phase).reshape(-1), dtype=np.uint16)
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, 81)
+        self._check(lib().ghom_set_material_svk(self._c, _ptr(ph), C.shape[0], _ptr(C)))
+
+    def set_stiffness_scale(self, s):
+        if s is None:
+            self._check(lib().ghom_set_stiffness_scale(self._c, None))
+        else:
+            s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1)
+            self._check(lib().ghom_set_stiffness_scale(self._c, _ptr(s)))
+
+    def set_control(self, mask):
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(9)
+        self._check(lib().ghom_set_control(self._c, _ptr(m)))
+
+    def set_history(self, target):
+        t = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 9)
+        self._check(lib().ghom_set_history(self._c, t.shape[0], _ptr(t)))
+
+    def set_tolerances(self, newton_tol=1e-6, cg_tol=1e-8, cg_forcing=0.0, max_newton=50, max_cg=5000):
+        self._check(lib().ghom_set_tolerances(self._c, newton_tol, cg_tol, cg_forcing, max_newton, max_cg))
+
+    def setup(self, w, precision_tols=None):
+        """Applies a workload dict of paper_1901_06531_amd.synth."""
+        if w["kind"] == "nh":
+            self.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+        else:
+            self.set_material_svk(w["phase"], w["C"])
+        if w.get("scale") is not None:
+            self.set_stiffness_scale(w["scale"])
+        self.set_control(w["mask"])
+        self.set_history(w["target"])
+        self.set_tolerances(w["newton_tol"], w["cg_tol"])
+        return self
+
+    # -- solve ---------------------------------------------------------------------------
+    def step(self):
+        info = StepInfo()
+        rc = lib().ghom_step(self._c, ctypes.byref(info))
+        self._check(rc)
+        return info.as_dict()
+
+    def resolve(self):
+        info = StepInfo()
+        self._check(lib().ghom_resolve(self._c, ctypes.byref(info)))
+        return info.as_dict()
+
+    def averages(self):
+        F = np.zeros(9)
+        P = np.zeros(9)
+        self._check(lib().ghom_get_averages(self._c, _ptr(F), _ptr(P)))
+        return F, P
+
+    def field(self, which=FIELD_F):
+        out = np.empty((9,) + self.shape)
+        self._check(lib().ghom_get_field(self._c, int(which), _ptr(out)))
+        return out
+
+    def save_state(self):
+        out = np.empty((9,) + self.shape)
+        k = ctypes.c_int()
+        self._check(lib().ghom_save_state(self._c, _ptr(out), ctypes.byref(k)))
+        return out, k.value
+
+    def load_state(self, F, k):
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape((9,) + self.shape)
+        self._check(lib().ghom_load_state(self._c, _ptr(F), int(k)))
+
+    def adjoint_grad_scale(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64).reshape(9)
+        out = np.empty(self.shape)
+        self._check(lib().ghom_adjoint_grad_scale(self._c, _ptr(a), _ptr(out)))
+        return out
+
+    # -- device entry points (torch tensors as device memory) ----------------------------
+    def apply_operator(self, v, out=None):
+        import torch
+        dt = torch.float64 if self.precision == FP64 else torch.float32
+        if v.dtype != dt:
+            raise TypeError("operator input must be %s" % dt)
+        out = torch.empty_like(v) if out is None else out
+        _torch_sync()
+        self._check(lib().ghom_apply_operator(self._c, _dev_ptr(v), _dev_ptr(out)))
+        return out
+
+    def apply_projection(self, v, out=None):
+        import torch
+        if v.dtype != torch.float64:
+            raise TypeError("projection input must be float64")
+        out = torch.empty_like(v) if out is None else out
+        _torch_sync()
+        self._check(lib().ghom_apply_projection(self._c, _dev_ptr(v), _dev_ptr(out)))
+        return out
+
+    def residual(self, Pbar):
+        import torch
+        out = torch.empty((9,) + self.shape, dtype=torch.float64, device="cuda")
+        Pb = np.ascontiguousarray(Pbar, dtype=np.float64).reshape(9)
+        _torch_sync()
+        self._check(lib().ghom_residual(self._c, _ptr(Pb), _dev_ptr(out)))
+        return out
+
+    # -- profiling -----------------------------------------------------------------------
+    def set_profiling(self, on=True):
+        self._check(lib().ghom_set_profiling(self._c, int(bool(on))))
+
+    def profile(self):
+        n = lib().ghom_profile_count(self._c)
+        out = {}
+        buf = ctypes.create_string_buffer(128)
+        for i in range(n):
+            cnt = ctypes.c_int()
+            ms = ctypes.c_double()
+            self._check(lib().ghom_profile_get(self._c, i, buf, 128, ctypes.byref(cnt), ctypes.byref(ms)))
+            out[buf.value.decode()] = (cnt.value, ms.value)
+        return out
+
+    def profile_reset(self):
+        self._check(lib().ghom_profile_reset(self._c))

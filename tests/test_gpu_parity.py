@@ -1,0 +1,270 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by element.
+
+FP64 bar: transforms and the operator agree to 1e-12 of the field's largest entry (the
+two sides differ only in rounding order; a 3-D transform pair of n^3 points has a
+round-off of order log2(n^3) * 2^-52 relative); averaged Newton histories to 1e-10.
+FP32-split bar: the operator inside CG agrees to 2e-5 of the largest entry (float32
+transforms and tangent); Newton results are stated per test.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ghom_oracle as go  # noqa: E402
+from paper_1901_06531_amd import ghom, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+MIXED = synth.mask_uniaxial(0)
+MASKS = {"stress": synth.mask_full_stress(), "strain": synth.mask_full_strain(), "mixed": MIXED}
+SHAPES = [(16, 16, 16), (32, 32, 32), (48, 48, 48), (24, 16, 32), (9, 27, 12), (8, 36, 6), (64, 64, 64)]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a, dtype=None):
+    dtype = torch.float64 if dtype is None else dtype
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def random_F(shape, g, amp=0.1):
+    F = np.broadcast_to(np.eye(3).reshape(9, 1, 1, 1), (9,) + shape) + amp * g.standard_normal((9,) + shape)
+    return np.ascontiguousarray(F)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("mask", ["stress", "strain", "mixed"])
+def test_projection_matches_oracle(shape, mask):
+    say("projection", shape, mask)
+    g = np.random.default_rng(1)
+    A = g.standard_normal((9,) + shape)
+    lengths = (1.0, 1.5, 0.75)
+    with ghom.Solver(shape, lengths) as s:
+        s.set_control(MASKS[mask])
+        out = s.apply_projection(dev(A)).cpu().numpy()
+    ref = go.apply_projection(A, MASKS[mask], lengths)
+    assert rel_err(out, ref) < 1e-12
+
+
+def _nh_setup(shape, g, nphase=3):
+    phase = g.integers(0, nphase, size=shape).astype(np.uint16)
+    mu = g.uniform(0.5, 5.0, nphase)
+    lam = g.uniform(0.5, 10.0, nphase)
+    scale = g.uniform(1.0, 3.0, size=shape)
+    return phase, mu, lam, scale
+
+
+def _svk_tables(n, seed):
+    R = synth.haar_rotations(n, seed)
+    return synth.rotate_C(synth.cubic_C(1.7, 1.2, 0.75), R).reshape(n, 81)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 32), (48, 48, 48), (9, 27, 12), (64, 64, 64)])
+@pytest.mark.parametrize("law", ["nh", "svk"])
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_operator_matches_oracle(shape, law, prec):
+    say("operator", shape, law, prec)
+    g = np.random.default_rng(2)
+    F = random_F(shape, g)
+    o = go.Oracle(shape)
+    with ghom.Solver(shape, precision=prec) as s:
+        if law == "nh":
+            phase, mu, lam, scale = _nh_setup(shape, g)
+            s.set_material_neohookean(phase, mu, lam)
+            s.set_stiffness_scale(scale)
+            o.set_material_neohookean(phase, mu, lam)
+            o.set_stiffness_scale(scale)
+        else:
+            phase = g.integers(0, 8, size=shape).astype(np.uint16)
+            C = _svk_tables(8, 4)
+            s.set_material_svk(phase, C)
+            o.set_material_svk(phase, C)
+        s.set_control(MIXED)
+        o.set_control(MIXED)
+        s.load_state(F, 0)
+        v = g.standard_normal((9,) + shape)
+        dt = torch.float64 if prec == ghom.FP64 else torch.float32
+        out = s.apply_operator(dev(v, dt)).double().cpu().numpy()
+    ref = o.apply_operator(v, F)
+    assert rel_err(out, ref) < (1e-12 if prec == ghom.FP64 else 2e-5)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32)])
+def test_residual_and_stress_match_oracle(shape):
+    say("residual", shape)
+    g = np.random.default_rng(3)
+    F = random_F(shape, g)
+    phase, mu, lam, scale = _nh_setup(shape, g)
+    Pbar = g.standard_normal(9) * 0.1
+    o = go.Oracle(shape)
+    o.set_material_neohookean(phase, mu, lam)
+    o.set_stiffness_scale(scale)
+    o.set_control(MIXED)
+    with ghom.Solver(shape) as s:
+        s.set_material_neohookean(phase, mu, lam)
+        s.set_stiffness_scale(scale)
+        s.set_control(MIXED)
+        s.load_state(F, 0)
+        b = s.residual(Pbar).cpu().numpy()
+        P = s.field(ghom.FIELD_P)
+        Favg, Pavg = s.averages()
+    Pref = o.stress(F)
+    assert rel_err(P, Pref) < 1e-13
+    np.testing.assert_allclose(Pavg, Pref.reshape(9, -1).mean(axis=1), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(Favg, F.reshape(9, -1).mean(axis=1), rtol=0, atol=1e-14)
+    ref = o.residual(Pref, np.where(MIXED > 0, Pbar, 0.0))
+    assert rel_err(b, ref) < 1e-12
+
+
+def _run_gpu(w, prec=ghom.FP64, nsteps=None, tols=None, forcing=0.0):
+    s = ghom.Solver(w["shape"], precision=prec)
+    s.setup(w)
+    nt, ct = (w["newton_tol"], w["cg_tol"]) if tols is None else tols
+    s.set_tolerances(nt, ct, forcing)
+    recs = []
+    n = len(w["target"]) if nsteps is None else nsteps
+    for k in range(n):
+        info = s.step()
+        F, P = s.averages()
+        recs.append((info, F, P))
+        say("  gpu step", k + 1, info["newton_iters"], info["cg_iters_total"], F[0], P[0])
+    return s, recs
+
+
+def test_sphere16_history_matches_oracle():
+    """The 16^3 centred-sphere cell, full stress control, P11 -> 0.1 in 5 increments."""
+    say("sphere16 history fp64")
+    gold = json.load(open(os.path.join(GOLD, "sphere16_history.json")))
+    s, recs = _run_gpu(synth.workload_sphere16())
+    s.close()
+    for (info, F, P), ref in zip(recs, gold["steps"]):
+        np.testing.assert_allclose(F, ref["F_avg"], rtol=0, atol=1e-10)
+        np.testing.assert_allclose(P, ref["P_avg"], rtol=0, atol=1e-10)
+        assert info["newton_iters"] == ref["newton_iters"]
+        assert abs(info["cg_iters_total"] - ref["cg_iters"]) <= 2
+
+
+def _oracle_run(w, nsteps, tols=None):
+    o = go.Oracle(w["shape"])
+    if w["kind"] == "nh":
+        o.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+    else:
+        o.set_material_svk(w["phase"], w["C"])
+    if w.get("scale") is not None:
+        o.set_stiffness_scale(w["scale"])
+    o.set_control(w["mask"])
+    o.set_history(w["target"])
+    nt, ct = (w["newton_tol"], w["cg_tol"]) if tols is None else tols
+    o.set_tolerances(nt, ct)
+    return o, go.run_history(o, nsteps)
+
+
+def test_mixed_particles_history_matches_oracle():
+    """Random-sphere neo-Hookean cell (32^3), transverse-stress-free mixed control."""
+    say("particles32 mixed fp64")
+    w = synth.workload_particles(n=32, seed=1, count=6, nsteps=20)
+    tols = (1e-10, 1e-11)
+    o, ref = _oracle_run(w, 2, tols)
+    s, recs = _run_gpu(w, nsteps=2, tols=tols)
+    Fg = s.field(ghom.FIELD_F)
+    s.close()
+    for (info, F, P), r in zip(recs, ref):
+        np.testing.assert_allclose(F, r.F_avg, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(P, r.P_avg, rtol=0, atol=1e-10)
+        assert info["newton_iters"] == r.newton_iters
+    assert np.max(np.abs(Fg - o.F)) < 1e-9
+
+
+def test_svk_polycrystal_matches_oracle():
+    """Small rotated-cubic SVK polycrystal under full stress control."""
+    say("polycrystal16 svk fp64")
+    w = synth.workload_polycrystal(n=16, ngrains=12, nsteps=4)
+    w["target"] = w["target"] * 5.0
+    tols = (1e-10, 1e-11)
+    o, ref = _oracle_run(w, 2, tols)
+    s, recs = _run_gpu(w, nsteps=2, tols=tols)
+    s.close()
+    for (info, F, P), r in zip(recs, ref):
+        np.testing.assert_allclose(P, r.P_avg, rtol=0, atol=1e-10)
+        C_gpu = F.reshape(3, 3).T @ F.reshape(3, 3)
+        C_ref = r.F_avg.reshape(3, 3).T @ r.F_avg.reshape(3, 3)
+        np.testing.assert_allclose(C_gpu, C_ref, rtol=0, atol=1e-10)
+
+
+def test_fp32_split_sphere16_matches_oracle():
+    """FP32-split reaches the FP64 solution: averages within 1e-9 of the oracle."""
+    say("sphere16 history fp32-split")
+    gold = json.load(open(os.path.join(GOLD, "sphere16_history.json")))
+    s, recs = _run_gpu(synth.workload_sphere16(), prec=ghom.FP32_SPLIT, forcing=1e-5)
+    s.close()
+    for (info, F, P), ref in zip(recs, gold["steps"]):
+        np.testing.assert_allclose(F, ref["F_avg"], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(P, ref["P_avg"], rtol=0, atol=1e-9)
+
+
+def test_adjoint_matches_oracle():
+    say("adjoint 12^3")
+    shape = (12, 12, 12)
+    g = np.random.default_rng(8)
+    phase = (g.uniform(size=shape) < 0.3).astype(np.uint16)
+    s_field = synth.smooth_scale_field(shape, 10, ell=0.2, lo=1.0, hi=3.0)
+    F_end = np.eye(3)
+    F_end[0, 0] = 1.05
+    w = dict(shape=shape, kind="nh", phase=phase, mu=[1.0, 10.0], lam=[2.0, 20.0], scale=s_field,
+             mask=MIXED, target=synth.history_mixed(MIXED, F_end.reshape(9), 2), newton_tol=1e-12, cg_tol=1e-13)
+    o, _ = _oracle_run(w, 2)
+    a = np.zeros(9)
+    a[4] = 1.0
+    ref = o.adjoint_grad_scale(a)
+    s, _ = _run_gpu(w)
+    got = s.adjoint_grad_scale(a)
+    s.close()
+    assert rel_err(got, ref) < 1e-8
+
+
+def test_failure_modes_are_reported():
+    say("failure modes")
+    shape = (8, 8, 8)
+    P_end = np.zeros(9)
+    P_end[0] = 0.1
+    with ghom.Solver(shape) as s:
+        s.set_material_neohookean(np.zeros(shape, np.uint16), [-1.0], [0.0])
+        s.set_control(synth.mask_full_stress())
+        s.set_history(synth.history_stress_ramp(P_end, 1))
+        with pytest.raises(ghom.GhomError) as e:
+            s.step()
+        assert e.value.name == "ESINGULAR"
+    with ghom.Solver(shape) as s:
+        F_end = np.eye(3)
+        F_end[0, 0] = -0.5
+        s.set_material_neohookean(np.zeros(shape, np.uint16), [1.0], [2.0])
+        s.set_control(synth.mask_full_strain())
+        s.set_history(F_end.reshape(1, 9))
+        with pytest.raises(ghom.GhomError) as e:
+            s.step()
+        assert e.value.name == "EDOMAIN"
+    with ghom.Solver(shape) as s:
+        g = np.random.default_rng(1)
+        s.set_material_neohookean((g.uniform(size=shape) < 0.3).astype(np.uint16), [1.0, 10.0], [2.0, 20.0])
+        s.set_control(synth.mask_full_stress())
+        s.set_history(synth.history_stress_ramp(P_end, 1))
+        s.set_tolerances(1e-6, 1e-8, 0.0, 50, 1)
+        with pytest.raises(ghom.GhomError) as e:
+            s.step()
+        assert e.value.name == "ENOTCONVERGED"
+    with ghom.Solver(shape) as s:
+        with pytest.raises(ghom.GhomError) as e:
+            s.step()
+        assert e.value.name == "ESTATE"
