@@ -1,0 +1,205 @@
+"""Benchmark: CG voxel-iterations/s and Newton step time at 256^3, FP32-split and FP64.
+
+Workload: 256^3 periodic Voronoi polycrystal (512 grains, seeded), rotated-cubic Saint
+Venant-Kirchhoff grains (C11, C12, C44) = (1.7, 1.2, 0.75), full stress control with P11
+cycled 0 -> +0.02 -> 0 -> -0.02 -> 0 over 40 increments (paper tolerances: Newton 1e-6,
+CG 1e-8).  A step is one load increment: the shift of the prescribed means, then Newton
+(constitutive update, FP64 residual, CG on G*(K:dF), Newton update) to convergence.
+
+value = N * (CG iterations in the timed increments) / (wall time of those increments), the
+whole-job throughput with every input resident in HBM.  Prints ONE JSON line on stdout;
+progress goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CG operator voxel-iters/s + Newton step time at 256^3, FP64 vs FP32-split"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def op_bytes(name, N, Nh, w, svk=True, update_p=True):
+    """Algorithmic HBM bytes of one launch of an operator pass (w = bytes of a real)."""
+    spec = 9 * Nh * 2 * w  # the 9-component half spectrum
+    field = 9 * N * w
+    if "yfwd" in name or "yinv" in name or "xproj" in name:
+        return 2 * spec
+    if "zfwd" in name:
+        state = (16 if svk else 12) * N * w + (2 * N if svk else 0)
+        return field * (3 if update_p else 1) + state + spec
+    if "zinv" in name:
+        return spec + 2 * field
+    return None
+
+
+def run_gpu(w, precision, steps, warmup, profile):
+    from paper_1901_06531_amd import ghom
+
+    s = ghom.Solver(w["shape"], precision=precision)
+    s.setup(w)
+    forcing = 0.0
+    s.set_tolerances(w["newton_tol"], w["cg_tol"], forcing)
+    for i in range(warmup):
+        info = s.step()
+        log("  warmup increment %d: newton %d cg %d  %.1f ms" % (i + 1, info["newton_iters"], info["cg_iters_total"],
+                                                                 info["t_total_ms"]))
+    import torch
+    torch.cuda.synchronize()
+    if profile:
+        s.profile_reset()
+        s.set_profiling(True)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        info = s.step()
+        infos.append(info)
+        log("  timed increment %d: newton %d cg %d  %.1f ms" % (warmup + i + 1, info["newton_iters"],
+                                                                info["cg_iters_total"], info["t_total_ms"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = s.profile() if profile else {}
+    F, P = s.averages()
+    s.close()
+    cg = sum(i["cg_iters_total"] for i in infos)
+    newton = sum(i["newton_iters"] for i in infos)
+    N = int(np.prod(w["shape"]))
+    return {
+        "voxel_iters_per_s": N * cg / wall,
+        "ms_per_increment": 1e3 * wall / steps,
+        "newton_step_ms": 1e3 * wall / max(newton, 1),
+        "cg_ms_per_iter": sum(i["t_cg_ms"] for i in infos) / max(cg, 1),
+        "cg_iters": cg,
+        "newton_iters": newton,
+        "F11": float(F[0]),
+        "P11": float(P[0]),
+    }, prof
+
+
+def cpu_baseline(w, max_seconds=30.0):
+    """The FP64 oracle timed on this host: CG iterations of the first Newton solve of the
+    given workload (a reduced-size instance of the benchmark's), as voxel-iterations/s."""
+    from oracle import ghom_oracle as go
+
+    o = go.Oracle(w["shape"])
+    o.set_material_svk(w["phase"], w["C"])
+    o.set_control(w["mask"])
+    o.set_history(w["target"])
+    o.set_tolerances(w["newton_tol"], w["cg_tol"], 0.0, 50, 1)
+    Pbar = np.where(w["mask"] > 0, w["target"][0], 0.0)
+    P = o.stress()
+    b = o.residual(P, Pbar)
+    t0 = time.perf_counter()
+    its = 0
+    while True:
+        try:
+            o.conjugate_gradient(b)
+        except go.NotConvergedError:
+            pass
+        its += 1
+        if time.perf_counter() - t0 > max_seconds / 2 or its >= 3:
+            break
+    dt = time.perf_counter() - t0
+    N = int(np.prod(w["shape"]))
+    return {"value": N * its / dt, "unit": "voxel-iters/s", "cores": go.WORKERS, "kind": "oracle",
+            "sample": "%d CG iteration(s) of the oracle's first Newton solve on the same %s workload "
+                      "(%.1f s)" % (its, w["name"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1901_06531_amd import ghom, synth
+
+    t0 = time.perf_counter()
+    w = synth.workload_polycrystal(n=args.grid)
+    N = int(np.prod(w["shape"]))
+    log("workload %s built in %.1f s" % (w["name"], time.perf_counter() - t0))
+
+    log("FP32-split run")
+    split, prof = run_gpu(w, ghom.FP32_SPLIT, args.steps, args.warmup, profile=True)
+    fp64 = None
+    if not args.no_fp64:
+        log("FP64 run")
+        fp64, _ = run_gpu(w, ghom.FP64, args.steps, args.warmup, profile=False)
+
+    # roofline of the dominant operator kernel, from the HIP-event timings of the timed region
+    nzh = w["shape"][2] // 2
+    Nh = w["shape"][0] * w["shape"][1] * nzh
+    op = {k: v for k, v in prof.items() if k.startswith("op_")}
+    roof = None
+    if op:
+        name = max(op, key=lambda k: op[k][1])
+        launches, ms = op[name]
+        wbytes = 4 if name.endswith("f32") else 8
+        per_launch = op_bytes(name, N, Nh, wbytes)
+        avg_s = ms / launches / 1e3
+        achieved = per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": name,
+                "avg_ms": round(ms / launches, 4), "bytes_per_launch": per_launch}
+        log("kernel times (timed region): " + ", ".join("%s %.3f ms x%d" % (k, v[1] / v[0], v[0])
+                                                        for k, v in sorted(op.items())))
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        # the oracle takes about a minute per CG iteration at 256^3: time it on the
+        # 128^3 instance of the same generator (same grain count, seeds and loading)
+        cpu = cpu_baseline(synth.workload_polycrystal(n=max(16, args.grid // 2)))
+
+    out = {
+        "metric": METRIC,
+        "value": round(split["voxel_iters_per_s"], 1),
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(split["ms_per_increment"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64-split",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "grid": list(w["shape"]), "grains": 512, "material": "svk-cubic",
+                   "control": "full stress, P11 triangle +-0.02 over 40 increments",
+                   "step": "one load increment", "precision": "fp32-split",
+                   "newton_tol": w["newton_tol"], "cg_tol": w["cg_tol"]},
+        "newton_step_ms": round(split["newton_step_ms"], 3),
+        "cg_ms_per_iter": round(split["cg_ms_per_iter"], 4),
+        "cg_iters": split["cg_iters"],
+        "newton_iters": split["newton_iters"],
+        "fp64": None if fp64 is None else {
+            "value": round(fp64["voxel_iters_per_s"], 1), "ms_per_step": round(fp64["ms_per_increment"], 3),
+            "newton_step_ms": round(fp64["newton_step_ms"], 3), "cg_ms_per_iter": round(fp64["cg_ms_per_iter"], 4),
+            "cg_iters": fp64["cg_iters"], "newton_iters": fp64["newton_iters"],
+            "split_vs_fp64_F11_diff": abs(fp64["F11"] - split["F11"])},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,10 +75,27 @@ _SIGS = {
 _lib = None
 
 
+def _bind_torch_runtime():
+    """Load torch's HIP runtime before libghom.so so that the process holds one runtime.
+
+    torch ships its own libamdhip64 / libhsa-runtime64 with the same sonames as the system
+    ones libghom.so is linked against.  Loaded first, torch's copies satisfy libghom.so's
+    dependencies; loaded second they would come in as a second runtime and torch would
+    then find no device.
+    """
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        _bind_torch_runtime()
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libghom.so not built at %s: run paper_1901_06531_amd/build.py" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
