@@ -44,6 +44,31 @@ def op_bytes(name, N, Nh, w, svk=True, update_p=True):
     return None
 
 
+def csrc_hash():
+    """Hash of the kernel sources: measured counters only count for the code they measured."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1901_06531_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter runs, or None if the kernels changed."""
+    path = os.path.join(ROOT, "profiles", "polycrystal256_hbm_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("csrc_sha256_16") != csrc_hash() or kernel not in d["kernels"]:
+        return None
+    k = d["kernels"][kernel]
+    return k["read_bytes"] + k["write_bytes"]
+
+
 def run_gpu(w, precision, steps, warmup, profile):
     from paper_1901_06531_amd import ghom
 
@@ -125,10 +150,27 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (5 times): the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": 1e3 * dt,
+                          "GBps_read_plus_write": 8 * n / dt / 1e9}), flush=True)
+        return
 
     from paper_1901_06531_amd import ghom, synth
 
@@ -157,7 +199,7 @@ def main():
         avg_s = ms / launches / 1e3
         achieved = per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": name,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
                 "avg_ms": round(ms / launches, 4), "bytes_per_launch": per_launch}
         log("kernel times (timed region): " + ", ".join("%s %.3f ms x%d" % (k, v[1] / v[0], v[0])
                                                         for k, v in sorted(op.items())))
