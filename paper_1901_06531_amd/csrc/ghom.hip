@@ -46,7 +46,6 @@ struct ghom_ctx {
   void* x = nullptr;
   void* r = nullptr;
   void* p = nullptr;
-  void* Ap = nullptr;
   void* state = nullptr;
   void* H = nullptr;  // spectrum, FP64 capacity
   // material
@@ -194,7 +193,7 @@ int launch_zfwd(ghom_ctx* c, const ZfwdArgs<T, TIN>& a, const char* name) {
   return grid;
 }
 
-template <typename T, typename TOUT>
+template <typename T, typename TOUT, bool CGU = false>
 int launch_zinv(ghom_ctx* c, const ZinvArgs<T, TOUT>& a, const char* name) {
   int grid = 0;
   with_split(c->g.nz, [&](auto s) {
@@ -203,7 +202,7 @@ int launch_zinv(ghom_ctx* c, const ZinvArgs<T, TOUT>& a, const char* name) {
     const long long nlines = (long long)c->g.nx * c->g.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
     timed(c, name, [&] {
-      hipLaunchKernelGGL((zinv_kernel<T, S::A, S::B, TOUT>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g, a);
+      hipLaunchKernelGGL((zinv_kernel<T, S::A, S::B, TOUT, CGU>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g, a);
     });
   });
   return grid;
@@ -271,36 +270,54 @@ int project64(ghom_ctx* c, const TIN* in, double* out, double scale, const doubl
   return launch_zinv<double, double>(c, zi, n5.c_str());
 }
 
-// Av = G*(K : v) in the CG type; when dot, partial sums of v . Av per zinv block
+// The operator A(v) = G*(K : v) in the CG type.
+//  plain (cg == false): Av written to `Av`.
+//  CG step (cg == true): v is the direction p (first updated to r + beta p when update_p);
+//    zfwd leaves per-block partials of p : K : p (= p . A p, p lying in the range of G*) for
+//    the alpha kernel, and zinv applies x += alpha p, r -= alpha A p with partials of r.r.
 template <typename T>
-int operator_apply(ghom_ctx* c, T* v, T* Av, const T* r, bool update_p, bool dot, const CGScalars* sc) {
+void operator_apply(ghom_ctx* c, T* v, T* Av, bool cg, bool update_p, const CGScalars* sc, int* grid_out) {
   ZfwdArgs<T, T> za{};
   za.p = v;
-  za.r = r;
+  za.r = reinterpret_cast<const T*>(c->r);
   za.update_p = update_p ? 1 : 0;
   za.state = reinterpret_cast<const T*>(c->state);
   za.phase = c->phase;
   za.C6 = c->mat;
+  za.has_scale = c->scale != nullptr;
+  za.partials = cg ? c->partials : nullptr;
   za.H = reinterpret_cast<cx<T>*>(c->H);
   za.tw = twid<T>(c, 2);
   za.sc = sc;
-  static const std::string pre = std::string("op_");
   const std::string t = tname<T>();
-  const std::string n1 = pre + "zfwd_" + t, n2 = pre + "yfwd_" + t, n3 = pre + "xproj_" + t,
-                    n4 = pre + "yinv_" + t, n5 = pre + "zinv_" + t;
-  if (c->kind == MAT_NH) launch_zfwd<T, Z_NH, T>(c, za, n1.c_str());
-  else launch_zfwd<T, Z_SVK, T>(c, za, n1.c_str());
+  const std::string n1 = "op_zfwd_" + t, n2 = "op_yfwd_" + t, n3 = "op_xproj_" + t, n4 = "op_yinv_" + t,
+                    n5 = "op_zinv_" + t;
+  int gz;
+  if (c->kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(c, za, n1.c_str());
+  else gz = launch_zfwd<T, Z_SVK, T>(c, za, n1.c_str());
+  if (grid_out) *grid_out = gz;
+  if (cg) {
+    timed(c, "cg_scalar", [&] {
+      hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gz, 1);
+    });
+  }
   launch_ypass<T, -1>(c, sc, n2.c_str());
   launch_xproj<T>(c, make_proj(c, 1.0, nullptr), sc, n3.c_str());
   launch_ypass<T, +1>(c, sc, n4.c_str());
   ZinvArgs<T, T> zi{};
   zi.H = reinterpret_cast<cx<T>*>(c->H);
-  zi.out = Av;
-  zi.dot_with = dot ? v : nullptr;
   zi.partials = c->partials;
   zi.tw = twid<T>(c, 2);
   zi.sc = sc;
-  return launch_zinv<T, T>(c, zi, n5.c_str());
+  if (cg) {
+    zi.x = reinterpret_cast<T*>(c->x);
+    zi.r = reinterpret_cast<T*>(c->r);
+    zi.p = v;
+    launch_zinv<T, T, true>(c, zi, n5.c_str());
+  } else {
+    zi.out = Av;
+    launch_zinv<T, T, false>(c, zi, n5.c_str());
+  }
 }
 
 void sync(ghom_ctx* c) { HIPCALL(hipStreamSynchronize(c->stream)); }
@@ -383,7 +400,6 @@ CGResult cg_solve(ghom_ctx* c, double rms_b, double* t_ms) {
   T* x = reinterpret_cast<T*>(c->x);
   T* r = reinterpret_cast<T*>(c->r);
   T* p = reinterpret_cast<T*>(c->p);
-  T* Ap = reinterpret_cast<T*>(c->Ap);
   hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(1), 0, c->stream, c->sc, tol * tol * (double)c->g.N, c->max_cg);
   HIPCALL(hipGetLastError());
   const int gi = vox_blocks(n9);
@@ -397,16 +413,10 @@ CGResult cg_solve(ghom_ctx* c, double rms_b, double* t_ms) {
   int chunk = c->g.N >= (1LL << 21) ? 1 : (c->g.N >= (1LL << 18) ? 2 : 8);
   for (;;) {
     for (int i = 0; i < chunk; ++i, ++enqueued) {
-      const int gz = operator_apply<T>(c, p, Ap, r, enqueued > 0, true, c->sc);
+      int gz = 0;
+      operator_apply<T>(c, p, nullptr, true, enqueued > 0, c->sc, &gz);
       timed(c, "cg_scalar", [&] {
-        hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gz, 1);
-      });
-      timed(c, (std::string("cg_update_") + tname<T>()).c_str(), [&] {
-        hipLaunchKernelGGL((cg_update_kernel<T>), dim3(gi), dim3(kVoxThreads), 0, c->stream, n9, x, r,
-                           (const T*)p, (const T*)Ap, c->sc, c->partials);
-      });
-      timed(c, "cg_scalar", [&] {
-        hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gi, 2);
+        hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gz, 2);
       });
     }
     HIPCALL(hipMemcpyAsync(c->host_sc, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
@@ -519,7 +529,7 @@ void dev_alloc(T** p, size_t count) {
 }
 
 void free_all(ghom_ctx* c) {
-  void* ptrs[] = {c->F, c->P, c->b, c->dF64, c->x, c->r, c->p, c->Ap, c->state, c->H, c->phase, c->scale,
+  void* ptrs[] = {c->F, c->P, c->b, c->dF64, c->x, c->r, c->p, c->state, c->H, c->phase, c->scale,
                   c->mat, c->partials, c->sc, c->flag, c->red, c->tw64[0], c->tw64[1], c->tw64[2],
                   c->tw32[0], c->tw32[1], c->tw32[2]};
   for (void* q : ptrs)
@@ -583,7 +593,6 @@ int ghom_create(ghom_ctx** out, int nx, int ny, int nz, double Lx, double Ly, do
     HIPCALL(hipMalloc(&c->x, n9 * c->tsz));
     HIPCALL(hipMalloc(&c->r, n9 * c->tsz));
     HIPCALL(hipMalloc(&c->p, n9 * c->tsz));
-    HIPCALL(hipMalloc(&c->Ap, n9 * c->tsz));
     HIPCALL(hipMalloc(&c->state, (size_t)kSVKState * c->g.N * c->tsz));
     HIPCALL(hipMalloc(&c->H, 9 * (size_t)c->g.Nh * sizeof(cx<double>)));
     dev_alloc(&c->phase, (size_t)c->g.N);
@@ -907,9 +916,9 @@ int ghom_apply_operator(ghom_ctx* c, const void* v_dev, void* Av_dev) {
     if (!v_dev || !Av_dev || v_dev == Av_dev) fail(GHOM_EINVAL, "bad operator buffers");
     if (!c->state_valid) constitutive(c);
     if (c->prec == GHOM_FP64)
-      operator_apply<double>(c, (double*)v_dev, (double*)Av_dev, nullptr, false, false, nullptr);
+      operator_apply<double>(c, (double*)v_dev, (double*)Av_dev, false, false, nullptr, nullptr);
     else
-      operator_apply<float>(c, (float*)v_dev, (float*)Av_dev, nullptr, false, false, nullptr);
+      operator_apply<float>(c, (float*)v_dev, (float*)Av_dev, false, false, nullptr, nullptr);
     sync(c);
     return GHOM_OK;
   });

@@ -108,10 +108,17 @@ template <typename T, int A, int B> struct ColCfg {
   static constexpr int TC = pow2_floor(cmax(1, cmin(64, cmin(256 / A, lds_cx<T>() / N))));
   static constexpr int NT = A * TC;
 };
-// z passes: LP pairs of real lines (9 components each) per workgroup
+// z passes: LP pairs of real lines (9 components each) per workgroup.  LP is at least
+// GHOM_ZLP (or enough for ~256 threads on short lines), bounded by 1024 threads and an
+// LDS budget of 80 KB.
+#ifndef GHOM_ZLP
+#define GHOM_ZLP 4
+#endif
+template <typename T> constexpr int zlds_cx() { return sizeof(T) == 8 ? 5120 : 10240; }
 template <typename T, int A, int B> struct ZCfg {
   static constexpr int N = A * B;
-  static constexpr int LP = cmax(1, cmin(256 / (9 * A), lds_cx<T>() / (9 * N)));
+  static constexpr int LP =
+      cmax(1, cmin(cmax(GHOM_ZLP, 256 / (9 * A)), cmin(1024 / (9 * A), zlds_cx<T>() / (9 * N))));
   static constexpr int NT = 9 * LP * A;
 };
 
@@ -211,9 +218,18 @@ struct ProjParams {
 
 __device__ __forceinline__ int signed_k(int k, int n) { return k <= (n - 1) / 2 ? k : k - n; }
 
+#ifndef XPROJ_ATTR
+#define XPROJ_ATTR
+#endif
+#ifndef XPROJ_UNROLL
+#define XPROJ_UNROLL nounroll
+#endif
+#define GHOM_PRAGMA(x) _Pragma(#x)
+// Row i of eq. (9) is B_ij = s xi_j with s = (sum_l A_il xi_l) / (xi.xi): only the scalar s
+// is carried between the forward and the inverse transforms of the three components.
 template <typename T, int A, int B>
 __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-xproj_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
+XPROJ_ATTR xproj_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
              const CGScalars* __restrict__ sc) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
@@ -226,74 +242,62 @@ xproj_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjPar
   const long long col = (long long)blockIdx.x * TC + j;
   const bool ok = col < ncols;
   const long long rs = ncols;
-  cx<T> v[3][B];
+  const int ky = ok ? (int)(col / g.nzh) : 0;
+  const int kz = ok ? (int)(col - (long long)ky * g.nzh) : 0;
+  const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
+  const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
+  const T xz = (T)(kz * g.invL[2]);
+  const T post = (T)pp.post;
+  // the thread holding kx = 0 (q = 0, e = 0) of column (ky, kz) = (0, 0) holds xi = 0
+  const bool hold0 = ok && ky == 0 && kz == 0 && q == 0;
+  auto xi_x = [&](int e) { return (T)(signed_k(q + A * e, g.nx) * g.invL[0]); };
+  cx<T> s[B];
+  cx<T> a0[3];
 #pragma unroll
+  for (int e = 0; e < B; ++e) s[e] = cx<T>{0, 0};
+GHOM_PRAGMA(XPROJ_UNROLL)
   for (int l = 0; l < 3; ++l) {
     const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + col;
+    cx<T> v[B];
 #pragma unroll
-    for (int e = 0; e < B; ++e) v[l][e] = ok ? src[(long long)(q + A * e) * rs] : cx<T>{0, 0};
-  }
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    four_step_first<A, B, -1>(v[l], q, tw);
+    for (int e = 0; e < B; ++e) v[e] = ok ? src[(long long)(q + A * e) * rs] : cx<T>{0, 0};
+    four_step_first<A, B, -1>(v, q, tw);
     if (l) __syncthreads();
 #pragma unroll
-    for (int c = 0; c < B; ++c) lds[(c * A + q) * TC + j] = v[l][c];
+    for (int c = 0; c < B; ++c) lds[(c * A + q) * TC + j] = v[c];
     __syncthreads();
-    four_step_second<A, B, -1>(v[l], q, [&](int c, int a) { return lds[(c * A + a) * TC + j]; });
-  }
-  // projection at each frequency held by this thread: kx = q + A e
-  {
-    const int ky = ok ? (int)(col / g.nzh) : 0;
-    const int kz = ok ? (int)(col - (long long)ky * g.nzh) : 0;
-    const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
-    const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
-    const T xz = (T)(kz * g.invL[2]);
-    const T post = (T)pp.post;
+    four_step_second<A, B, -1>(v, q, [&](int c, int a) { return lds[(c * A + a) * TC + j]; });
 #pragma unroll
-    for (int e = 0; e < B; ++e) {
-      const int kx = q + A * e;
-      const bool nyq = nyq_yz || ((g.nx % 2 == 0) && kx == g.nx / 2);
-      const T xx = (T)(signed_k(kx, g.nx) * g.invL[0]);
-      const T xi2 = xx * xx + xy * xy + xz * xz;
-      if (nyq) {
-#pragma unroll
-        for (int l = 0; l < 3; ++l) v[l][e] = cx<T>{0, 0};
-      } else if (kx == 0 && ky == 0 && kz == 0) {
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          const int c = 3 * row + l;
-          if ((pp.mask >> c) & 1u) {
-            v[l][e].re = (v[l][e].re - (T)pp.off[c]) * post;
-            v[l][e].im = v[l][e].im * post;
-          } else {
-            v[l][e] = cx<T>{0, 0};
-          }
-        }
-      } else {
-        const T inv = post / xi2;
-        const cx<T> s = (v[0][e] * xx + v[1][e] * xy + v[2][e] * xz) * inv;
-        v[0][e] = s * xx;
-        v[1][e] = s * xy;
-        v[2][e] = s * xz;
-      }
-    }
+    for (int e = 0; e < B; ++e) s[e] = s[e] + v[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
+    a0[l] = v[0];
   }
 #pragma unroll
+  for (int e = 0; e < B; ++e) {
+    const int kx = q + A * e;
+    const bool nyq = nyq_yz || ((g.nx % 2 == 0) && kx == g.nx / 2);
+    const T xx = xi_x(e);
+    const T xi2 = xx * xx + xy * xy + xz * xz;
+    s[e] = (nyq || xi2 == (T)0) ? cx<T>{0, 0} : s[e] * (post / xi2);
+  }
+GHOM_PRAGMA(XPROJ_UNROLL)
   for (int l = 0; l < 3; ++l) {
+    cx<T> v[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) v[e] = s[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
+    if (hold0) {  // xi = 0: eq. (22) keeps stress-controlled components (minus P-bar)
+      const int c = 3 * row + l;
+      v[0] = ((pp.mask >> c) & 1u) ? cx<T>{(a0[l].re - (T)pp.off[c]) * post, a0[l].im * post} : cx<T>{0, 0};
+    }
     __syncthreads();
-    four_step_second_inv<A, B, +1>(v[l], q, tw, [&](int c, int a, cx<T> z) { lds[(c * A + a) * TC + j] = z; });
+    four_step_second_inv<A, B, +1>(v, q, tw, [&](int c, int a, cx<T> z) { lds[(c * A + a) * TC + j] = z; });
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < B; ++b) v[l][b] = lds[(b * A + q) * TC + j];
-    dft<B, +1>(v[l]);
-  }
-  if (ok) {
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
+    for (int b = 0; b < B; ++b) v[b] = lds[(b * A + q) * TC + j];
+    dft<B, +1>(v);
+    if (ok) {
       cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + col;
 #pragma unroll
-      for (int e = 0; e < B; ++e) dst[(long long)(q + A * e) * rs] = v[l][e];
+      for (int e = 0; e < B; ++e) dst[(long long)(q + A * e) * rs] = v[e];
     }
   }
 }
@@ -374,6 +378,8 @@ struct ZfwdArgs {
   const T* state;             // tangent state planes
   const uint16_t* phase;      // SVK: phase of each voxel
   const double* C6;           // SVK: per-phase 6x6 Voigt stiffness
+  int has_scale;              // SVK: state plane 15 holds s(x) (else s = 1)
+  double* partials;           // nullable: per-block partial of sum p : (K : p) (FP64)
   cx<T>* H;                   // spectrum out
   const cx<T>* tw;            // z twiddles
   const CGScalars* sc;        // early exit / beta (nullable)
@@ -385,10 +391,12 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B;
   __shared__ cx<T> lds[9 * LP * NZ];
+  __shared__ double red[(NT + 63) / 64];
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
   const long long line0 = (long long)blockIdx.x * (2 * LP);
   T* ldsr = reinterpret_cast<T*>(lds);
+  double pkp = 0.0;
   const T beta = (MODE != Z_PLAIN && args.update_p) ? (T)args.sc->beta : (T)0;
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
@@ -419,8 +427,13 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
         } else {
           T st[kSVKState];
 #pragma unroll
-          for (int k = 0; k < kSVKState; ++k) st[k] = args.state[k * g.N + vox];
+          for (int k = 0; k < kSVKState - 1; ++k) st[k] = args.state[k * g.N + vox];
+          st[kSVKState - 1] = args.has_scale ? args.state[(kSVKState - 1) * g.N + vox] : (T)1;
           tangent_svk(st, args.C6 + 36 * args.phase[vox], d, val);
+        }
+        if (args.partials) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) pkp += (double)d[c] * (double)val[c];
         }
       }
     } else {
@@ -461,6 +474,10 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
     if (l0 < nlines) args.H[c * g.Nh + l0 * nzh + kz] = Ak;
     if (l0 + 1 < nlines) args.H[c * g.Nh + (l0 + 1) * nzh + kz] = Bk;
   }
+  if (args.partials) {
+    const double t = block_sum<NT>(pkp, red);
+    if (threadIdx.x == 0) args.partials[blockIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -469,14 +486,17 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
 template <typename T, typename TOUT>
 struct ZinvArgs {
   const cx<T>* H;
-  TOUT* out;                  // 9 planes
+  TOUT* out;                  // 9 planes (plain mode)
+  TOUT* x;                    // CG mode: x += alpha p, r -= alpha A p, partial r.r
+  TOUT* r;
+  const TOUT* p;
   const TOUT* dot_with;       // nullable: partial sum of out . dot_with per block
   double* partials;           // one value per block when dot_with != nullptr
   const cx<T>* tw;
   const CGScalars* sc;        // early exit (nullable)
 };
 
-template <typename T, int A, int B, typename TOUT>
+template <typename T, int A, int B, typename TOUT, bool CGU>
 __global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
 zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
   using Cfg = ZCfg<T, A, B>;
@@ -517,6 +537,7 @@ zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
   // phase 3: real lines out
   const T* ldsr = reinterpret_cast<const T*>(lds);
   double acc = 0.0;
+  const TOUT alpha = CGU ? (TOUT)args.sc->alpha : (TOUT)0;
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
     const long long line = line0 + lp;
@@ -526,11 +547,20 @@ zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * NZ + z) + part];
-      args.out[c * g.N + vox] = o;
-      if (args.dot_with) acc += (double)o * (double)args.dot_with[c * g.N + vox];
+      const long long i = c * g.N + vox;
+      if constexpr (CGU) {
+        const TOUT xv = args.x[i] + alpha * args.p[i];
+        const TOUT rv = args.r[i] - alpha * o;
+        args.x[i] = xv;
+        args.r[i] = rv;
+        acc += (double)rv * (double)rv;
+      } else {
+        args.out[i] = o;
+        if (args.dot_with) acc += (double)o * (double)args.dot_with[i];
+      }
     }
   }
-  if (args.dot_with) {
+  if (CGU || args.dot_with) {
     const double s = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) args.partials[blockIdx.x] = s;
   }
@@ -614,7 +644,7 @@ constitutive_kernel(Geo g, const double* __restrict__ F, double* __restrict__ P,
       for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)f[c];
 #pragma unroll
       for (int I = 0; I < 6; ++I) state[(9 + I) * g.N + v] = (TS)S[I];
-      state[15 * g.N + v] = (TS)s;
+      if (scale) state[15 * g.N + v] = (TS)s;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -647,25 +677,6 @@ cg_init_kernel(long long n, const double* __restrict__ b, T* __restrict__ x, T* 
     r[i] = v;
     p[i] = v;
     acc += (double)v * (double)v;
-  }
-  const double s = block_sum<kVoxThreads>(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-// x += alpha p, r -= alpha Ap, partial r.r
-template <typename T>
-__global__ void __launch_bounds__(kVoxThreads)
-cg_update_kernel(long long n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                 const T* __restrict__ Ap, const CGScalars* __restrict__ sc, double* __restrict__ partials) {
-  __shared__ double red[kVoxThreads / 64];
-  if (sc->done) return;
-  const T alpha = (T)sc->alpha;
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kVoxThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVoxThreads) {
-    x[i] += alpha * p[i];
-    const T rn = r[i] - alpha * Ap[i];
-    r[i] = rn;
-    acc += (double)rn * (double)rn;
   }
   const double s = block_sum<kVoxThreads>(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
