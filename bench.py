@@ -37,10 +37,10 @@ def op_bytes(name, N, Nh, w, svk=True, update_p=True):
     if "yfwd" in name or "yinv" in name or "xproj" in name:
         return 2 * spec
     if "zfwd" in name:
-        state = (16 if svk else 12) * N * w + (2 * N if svk else 0)
+        state = (15 if svk else 12) * N * w + (2 * N if svk else 0)  # SVK: F, S (no scale plane)
         return field * (3 if update_p else 1) + state + spec
-    if "zinv" in name:
-        return spec + 2 * field
+    if "zinv" in name:  # CG step: spectrum in; x, r, p in; x, r out
+        return spec + 5 * field
     return None
 
 
@@ -74,6 +74,7 @@ def run_gpu(w, precision, steps, warmup, profile):
 
     s = ghom.Solver(w["shape"], precision=precision)
     s.setup(w)
+    xproj = {"f64": s.get_option(ghom.OPT_XPROJ_F64), "f32": s.get_option(ghom.OPT_XPROJ_F32)}
     forcing = 0.0
     s.set_tolerances(w["newton_tol"], w["cg_tol"], forcing)
     for i in range(warmup):
@@ -109,6 +110,7 @@ def run_gpu(w, precision, steps, warmup, profile):
         "newton_iters": newton,
         "F11": float(F[0]),
         "P11": float(P[0]),
+        "xproj_variant": xproj,
     }, prof
 
 
@@ -232,6 +234,7 @@ def main():
         "cg_ms_per_iter": round(split["cg_ms_per_iter"], 4),
         "cg_iters": split["cg_iters"],
         "newton_iters": split["newton_iters"],
+        "xproj_variant": split["xproj_variant"],
         "fp64": None if fp64 is None else {
             "value": round(fp64["voxel_iters_per_s"], 1), "ms_per_step": round(fp64["ms_per_increment"], 3),
             "newton_step_ms": round(fp64["newton_step_ms"], 3), "cg_ms_per_iter": round(fp64["cg_ms_per_iter"], 4),

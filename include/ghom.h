@@ -161,6 +161,24 @@ int ghom_apply_projection(ghom_ctx *ctx, const double *in_dev, double *out_dev);
  * stress-controlled components are used).  Also refreshes P and the tangent state. */
 int ghom_residual(ghom_ctx *ctx, const double Pbar[9], double *out_dev);
 
+/* ---- kernel choices ----------------------------------------------------------------- */
+
+/* Keys of ghom_set_option / ghom_get_option. */
+enum {
+  GHOM_OPT_XPROJ_F64 = 1,  /* x-pass (transform along x + projection) variant, float64    */
+  GHOM_OPT_XPROJ_F32 = 2   /* the same for the float32 transforms of GHOM_FP32_SPLIT      */
+};
+
+/* Selects a kernel variant.  For the x-pass keys: 0 = pick the faster variant by timing
+ * both on this GPU and grid (done by ghom_create; setting 0 re-times), 1 = "rows" (one
+ * thread transforms the three components of a tensor row in turn), 2 = "groups" (three
+ * thread groups, one per component, meeting in LDS).  Both compute the same operator. */
+int ghom_set_option(ghom_ctx *ctx, int key, int value);
+
+/* Reads the current value of an option (for the x-pass keys: the variant in use, 1 or 2,
+ * once tuned). */
+int ghom_get_option(ghom_ctx *ctx, int key, int *value);
+
 /* ---- measurement ------------------------------------------------------------------ */
 
 /* Enables (1) or disables (0) HIP-event timing of every kernel launch of the context. */

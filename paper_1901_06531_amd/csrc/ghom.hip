@@ -54,6 +54,7 @@ struct ghom_ctx {
   uint16_t* phase = nullptr;
   double* scale = nullptr;
   double* mat = nullptr;  // NH: (mu, lam) per phase; SVK: 36 Voigt values per phase
+  float* mat32 = nullptr; // SVK: the Voigt table in float32 (tangent of the FP32 CG)
   bool state_valid = false;
   // twiddles W_n^k = exp(-2 pi i k / n) per axis
   cx<double>* tw64[3] = {nullptr, nullptr, nullptr};
@@ -77,6 +78,8 @@ struct ghom_ctx {
   double Favg[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double Pavg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::string err;
+  // x-pass variant per precision ([0] float64, [1] float32): 0 untuned, 1 rows, 2 groups
+  int xproj_var[2] = {0, 0};
   // profiling
   bool prof = false;
   std::map<std::string, ProfRec> prof_recs;
@@ -168,6 +171,10 @@ template <typename T> const char* tname();
 template <> const char* tname<double>() { return "f64"; }
 template <> const char* tname<float>() { return "f32"; }
 
+template <typename T> const T* mat_table(ghom_ctx* c);
+template <> const double* mat_table<double>(ghom_ctx* c) { return c->mat; }
+template <> const float* mat_table<float>(ghom_ctx* c) { return c->mat32; }
+
 template <typename T> cx<T>* twid(ghom_ctx* c, int axis);
 template <> cx<double>* twid<double>(ghom_ctx* c, int axis) { return c->tw64[axis]; }
 template <> cx<float>* twid<float>(ghom_ctx* c, int axis) { return c->tw32[axis]; }
@@ -222,18 +229,67 @@ void launch_ypass(ghom_ctx* c, const CGScalars* sc, const char* name) {
   });
 }
 
+enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2 };
+
+template <typename T> int& xproj_choice(ghom_ctx* c) { return c->xproj_var[sizeof(T) == 8 ? 0 : 1]; }
+
 template <typename T>
-void launch_xproj(ghom_ctx* c, const ProjParams& pp, const CGScalars* sc, const char* name) {
+void launch_xproj_variant(ghom_ctx* c, int variant, const ProjParams& pp, const CGScalars* sc) {
   with_split(c->g.nx, [&](auto s) {
     using S = decltype(s);
-    using Cfg = ColCfg<T, S::A, S::B>;
     const long long ncols = (long long)c->g.ny * c->g.nzh;
-    const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-    timed(c, name, [&] {
-      hipLaunchKernelGGL((xproj_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g,
+    if (variant == XPROJ_ROWS) {
+      using Cfg = ColCfg<T, S::A, S::B>;
+      const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+      hipLaunchKernelGGL((xproj_rows_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g,
                          reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 0), pp, sc);
-    });
+    } else {
+      using Cfg = XCfg<T, S::A, S::B>;
+      const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+      hipLaunchKernelGGL((xproj_groups_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g,
+                         reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 0), pp, sc);
+    }
   });
+}
+
+template <typename T>
+void launch_xproj(ghom_ctx* c, const ProjParams& pp, const CGScalars* sc, const char* name) {
+  const int v = xproj_choice<T>(c);
+  timed(c, name, [&] { launch_xproj_variant<T>(c, v == XPROJ_TUNED ? XPROJ_ROWS : v, pp, sc); });
+}
+
+// Autotuner: times both x-pass variants on the (scratch) spectrum buffer with HIP events
+// and keeps the faster one for this precision and grid.  Runs at context creation, when the
+// spectrum holds no data; the result is reported by ghom_get_option.
+template <typename T>
+void tune_xproj(ghom_ctx* c) {
+  ProjParams pp{};
+  pp.post = 1.0 / (double)c->g.N;
+  hipEvent_t e0 = get_event(c), e1 = get_event(c);
+  float best = 0.f;
+  int best_v = XPROJ_ROWS;
+  for (int v : {XPROJ_ROWS, XPROJ_GROUPS}) {
+    launch_xproj_variant<T>(c, v, pp, nullptr);  // warm-up
+    HIPCALL(hipGetLastError());
+    float tmin = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCALL(hipEventRecord(e0, c->stream));
+      launch_xproj_variant<T>(c, v, pp, nullptr);
+      HIPCALL(hipGetLastError());
+      HIPCALL(hipEventRecord(e1, c->stream));
+      HIPCALL(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCALL(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 0 || ms < tmin) tmin = ms;
+    }
+    if (v == XPROJ_ROWS || tmin < best) {
+      best = tmin;
+      best_v = v;
+    }
+  }
+  c->ev_pool.push_back(e0);
+  c->ev_pool.push_back(e1);
+  xproj_choice<T>(c) = best_v;
 }
 
 ProjParams make_proj(ghom_ctx* c, double scale, const double* Pbar) {
@@ -283,7 +339,7 @@ void operator_apply(ghom_ctx* c, T* v, T* Av, bool cg, bool update_p, const CGSc
   za.update_p = update_p ? 1 : 0;
   za.state = reinterpret_cast<const T*>(c->state);
   za.phase = c->phase;
-  za.C6 = c->mat;
+  za.C6 = mat_table<T>(c);
   za.has_scale = c->scale != nullptr;
   za.partials = cg ? c->partials : nullptr;
   za.H = reinterpret_cast<cx<T>*>(c->H);
@@ -323,6 +379,11 @@ void operator_apply(ghom_ctx* c, T* v, T* Av, bool cg, bool update_p, const CGSc
 void sync(ghom_ctx* c) { HIPCALL(hipStreamSynchronize(c->stream)); }
 
 __global__ void zero_int_kernel(int* f) { *f = 0; }
+
+__global__ void fill_zero_kernel(long long n, double* p) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
 
 // ------------------------------------------------------------------ method steps -------
 // constitutive update: P, tangent state, <F>, <P>; EDOMAIN if det F <= 0 anywhere
@@ -530,7 +591,7 @@ void dev_alloc(T** p, size_t count) {
 
 void free_all(ghom_ctx* c) {
   void* ptrs[] = {c->F, c->P, c->b, c->dF64, c->x, c->r, c->p, c->state, c->H, c->phase, c->scale,
-                  c->mat, c->partials, c->sc, c->flag, c->red, c->tw64[0], c->tw64[1], c->tw64[2],
+                  c->mat, c->mat32, c->partials, c->sc, c->flag, c->red, c->tw64[0], c->tw64[1], c->tw64[2],
                   c->tw32[0], c->tw32[1], c->tw32[2]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -622,6 +683,12 @@ int ghom_create(ghom_ctx** out, int nx, int ny, int nz, double Lx, double Ly, do
       HIPCALL(hipMemcpy(c->tw32[a], t32.data(), ns[a] * sizeof(cx<float>), hipMemcpyHostToDevice));
     }
     reset_state(c);
+    // zero spectrum, then pick the x-pass variants by timing them on it
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(vox_blocks(18 * c->g.Nh)), dim3(kVoxThreads), 0, c->stream,
+                       18 * c->g.Nh, reinterpret_cast<double*>(c->H));
+    HIPCALL(hipGetLastError());
+    tune_xproj<double>(c);
+    if (precision == GHOM_FP32_SPLIT) tune_xproj<float>(c);
     sync(c);
     return GHOM_OK;
   });
@@ -695,9 +762,14 @@ int ghom_set_material_svk(ghom_ctx* c, const uint16_t* phase, int nphase, const 
         for (int J = 0; J < 6; ++J) tab[36 * (size_t)ph + 6 * I + J] = at(vi[I], vj[I], vi[J], vj[J]);
     }
     if (c->mat) HIPCALL(hipFree(c->mat));
+    if (c->mat32) HIPCALL(hipFree(c->mat32));
     c->mat = nullptr;
+    c->mat32 = nullptr;
     dev_alloc(&c->mat, tab.size());
     HIPCALL(hipMemcpy(c->mat, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<float> tab32(tab.begin(), tab.end());
+    dev_alloc(&c->mat32, tab32.size());
+    HIPCALL(hipMemcpy(c->mat32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice));
     HIPCALL(hipMemcpy(c->phase, phase, (size_t)c->g.N * sizeof(uint16_t), hipMemcpyHostToDevice));
     c->kind = MAT_SVK;
     c->nphase = nphase;
@@ -943,6 +1015,39 @@ int ghom_residual(ghom_ctx* c, const double Pbar[9], double* out_dev) {
     constitutive(c);
     project64<double>(c, c->P, out_dev, -1.0, pb, false, "res");
     sync(c);
+    return GHOM_OK;
+  });
+}
+
+int ghom_set_option(ghom_ctx* c, int key, int value) {
+  return guard(c, [&]() -> int {
+    if (key == GHOM_OPT_XPROJ_F64 || key == GHOM_OPT_XPROJ_F32) {
+      if (value < XPROJ_TUNED || value > XPROJ_GROUPS) fail(GHOM_EINVAL, "x-pass variant must be 0, 1 or 2");
+      int& slot = c->xproj_var[key == GHOM_OPT_XPROJ_F64 ? 0 : 1];
+      if (value == XPROJ_TUNED) {
+        slot = XPROJ_TUNED;
+        sync(c);
+        hipLaunchKernelGGL(fill_zero_kernel, dim3(vox_blocks(18 * c->g.Nh)), dim3(kVoxThreads), 0, c->stream,
+                           18 * c->g.Nh, reinterpret_cast<double*>(c->H));
+        HIPCALL(hipGetLastError());
+        if (key == GHOM_OPT_XPROJ_F64) tune_xproj<double>(c);
+        else tune_xproj<float>(c);
+        sync(c);
+      } else {
+        slot = value;
+      }
+      return GHOM_OK;
+    }
+    fail(GHOM_EINVAL, "unknown option");
+  });
+}
+
+int ghom_get_option(ghom_ctx* c, int key, int* value) {
+  return guard(c, [&]() -> int {
+    if (!value) fail(GHOM_EINVAL, "null output");
+    if (key == GHOM_OPT_XPROJ_F64) *value = c->xproj_var[0];
+    else if (key == GHOM_OPT_XPROJ_F32) *value = c->xproj_var[1];
+    else fail(GHOM_EINVAL, "unknown option");
     return GHOM_OK;
   });
 }

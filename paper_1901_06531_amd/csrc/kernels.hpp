@@ -102,24 +102,31 @@ constexpr int pow2_floor(int v) {
 // LDS budget per workgroup, in complex values
 template <typename T> constexpr int lds_cx() { return sizeof(T) == 8 ? 4096 : 8192; }
 
-// column passes: A threads per line, TC lines per workgroup
-template <typename T, int A, int B> struct ColCfg {
+// column passes: A threads per line, TC lines per workgroup (at most TCMAX)
+template <typename T, int A, int B, int TCMAX = 64, int MAXT = 256> struct ColCfg {
   static constexpr int N = A * B;
-  static constexpr int TC = pow2_floor(cmax(1, cmin(64, cmin(256 / A, lds_cx<T>() / N))));
+  static constexpr int TC = pow2_floor(cmax(1, cmin(TCMAX, cmin(MAXT / A, lds_cx<T>() / N))));
   static constexpr int NT = A * TC;
+  // LDS stride between the exchange rows of consecutive c: one extra row of TC values
+  // moves lanes of neighbouring c to the other half of the banks (float32)
+  static constexpr int RS = A * TC + TC;
+  static constexpr int LDS = B * RS;
 };
+
 // z passes: LP pairs of real lines (9 components each) per workgroup.  LP is at least
 // GHOM_ZLP (or enough for ~256 threads on short lines), bounded by 1024 threads and an
 // LDS budget of 80 KB.
 #ifndef GHOM_ZLP
-#define GHOM_ZLP 4
+#define GHOM_ZLP 1
 #endif
 template <typename T> constexpr int zlds_cx() { return sizeof(T) == 8 ? 5120 : 10240; }
 template <typename T, int A, int B> struct ZCfg {
   static constexpr int N = A * B;
+  static constexpr int R = N + B;  // LDS complex values per line: exchange rows padded to A + 1
   static constexpr int LP =
-      cmax(1, cmin(cmax(GHOM_ZLP, 256 / (9 * A)), cmin(1024 / (9 * A), zlds_cx<T>() / (9 * N))));
-  static constexpr int NT = 9 * LP * A;
+      cmax(1, cmin(cmax(GHOM_ZLP, 256 / (9 * A)), cmin(1024 / (9 * A), zlds_cx<T>() / (9 * R))));
+  static constexpr int NF = 9 * LP * A;           // threads of the transform phase
+  static constexpr int NT = (NF + 63) / 64 * 64;  // whole wavefronts
 };
 
 // ---------------------------------------------------------------------------------
@@ -183,7 +190,8 @@ __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
 ypass_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const CGScalars* __restrict__ sc) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
-  __shared__ cx<T> lds[A * B * TC];
+  constexpr int RS = Cfg::RS;
+  __shared__ cx<T> lds[Cfg::LDS];
   if (sc && sc->done) return;
   const int j = threadIdx.x % TC;
   const int q = threadIdx.x / TC;
@@ -198,9 +206,9 @@ ypass_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const C
   for (int e = 0; e < B; ++e) v[e] = ok ? H[base + (long long)(q + A * e) * rs] : cx<T>{0, 0};
   four_step_first<A, B, DIR>(v, q, tw);
 #pragma unroll
-  for (int c = 0; c < B; ++c) lds[(c * A + q) * TC + j] = v[c];
+  for (int c = 0; c < B; ++c) lds[c * RS + q * TC + j] = v[c];
   __syncthreads();
-  four_step_second<A, B, DIR>(v, q, [&](int c, int a) { return lds[(c * A + a) * TC + j]; });
+  four_step_second<A, B, DIR>(v, q, [&](int c, int a) { return lds[c * RS + a * TC + j]; });
   if (ok) {
 #pragma unroll
     for (int e = 0; e < B; ++e) H[base + (long long)(q + A * e) * rs] = v[e];
@@ -218,22 +226,114 @@ struct ProjParams {
 
 __device__ __forceinline__ int signed_k(int k, int n) { return k <= (n - 1) / 2 ? k : k - n; }
 
-#ifndef XPROJ_ATTR
-#define XPROJ_ATTR
+// x pass with the modified projection.  Row i of eq. (9) is B_ij = s xi_j with
+// s = (sum_l A_il xi_l) / (xi.xi), so the forward transforms of a row's three components
+// only meet in s.  Two variants (the faster one is picked per precision and grid at run
+// time):
+//  "groups": a workgroup takes TC columns (ky, kz) of one tensor row; thread group l in
+//    {0, 1, 2} transforms component 3i + l along x, the groups form s through LDS, then
+//    each transforms s xi_l back;
+//  "rows": one thread transforms all three components of its columns in turn.
+#ifndef XPROJ_TC
+#define XPROJ_TC 0
 #endif
-#ifndef XPROJ_UNROLL
-#define XPROJ_UNROLL nounroll
+#ifndef XPROJ_TCMAX
+#define XPROJ_TCMAX 16
 #endif
-#define GHOM_PRAGMA(x) _Pragma(#x)
-// Row i of eq. (9) is B_ij = s xi_j with s = (sum_l A_il xi_l) / (xi.xi): only the scalar s
-// is carried between the forward and the inverse transforms of the three components.
+template <typename T, int A, int B> struct XCfg {
+  static constexpr int N = A * B;
+  // three groups share the LDS budget: TC columns per group, power of two
+  static constexpr int fit(int tc) {  // largest power of two <= tc whose LDS stays under 100 KB
+    while (tc > 1 && 3 * B * (A * tc + tc) * (int)sizeof(cx<T>) > 100 * 1024) tc /= 2;
+    return tc;
+  }
+  static constexpr int TC_AUTO = fit(pow2_floor(cmax(1, cmin(XPROJ_TCMAX, 128 / A))));
+  static constexpr int TC = XPROJ_TC > 0 ? fit(XPROJ_TC) : TC_AUTO;
+  static constexpr int RS = A * TC + TC;   // padded stride between exchange rows
+  static constexpr int REG = B * RS;       // LDS complex values per group
+  static constexpr int NG = A * TC;        // threads per group
+  static constexpr int NT = 3 * NG;
+};
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__((XCfg<T, A, B>::NT))
+xproj_groups_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
+             const CGScalars* __restrict__ sc) {
+  using Cfg = XCfg<T, A, B>;
+  constexpr int TC = Cfg::TC, RS = Cfg::RS, REG = Cfg::REG;
+  __shared__ cx<T> lds[3 * REG];
+  if (sc && sc->done) return;
+  const int l = threadIdx.x / Cfg::NG;          // component of the row handled by this thread
+  const int tl = threadIdx.x - l * Cfg::NG;
+  const int j = tl % TC;
+  const int q = tl / TC;
+  const int row = blockIdx.y;
+  const int comp = 3 * row + l;
+  cx<T>* E = lds + l * REG;                     // this group's exchange region
+  const long long ncols = (long long)g.ny * g.nzh;
+  const long long col = (long long)blockIdx.x * TC + j;
+  const bool ok = col < ncols;
+  const long long rs = ncols;
+  const int ky = ok ? (int)(col / g.nzh) : 0;
+  const int kz = ok ? (int)(col - (long long)ky * g.nzh) : 0;
+  const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
+  const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
+  const T xz = (T)(kz * g.invL[2]);
+  const T post = (T)pp.post;
+  auto xi_x = [&](int e) { return (T)(signed_k(q + A * e, g.nx) * g.invL[0]); };
+  const long long cbase = (long long)comp * g.Nh + col;
+  cx<T> v[B];
+#pragma unroll
+  for (int e = 0; e < B; ++e) v[e] = ok ? H[cbase + (long long)(q + A * e) * rs] : cx<T>{0, 0};
+  // forward transform along x of this group's component
+  four_step_first<A, B, -1>(v, q, tw);
+#pragma unroll
+  for (int c = 0; c < B; ++c) E[c * RS + q * TC + j] = v[c];
+  __syncthreads();
+  four_step_second<A, B, -1>(v, q, [&](int c, int a) { return E[c * RS + a * TC + j]; });
+  const cx<T> a0 = v[0];  // value at kx = q (= 0 for q = 0)
+  // publish xi_l X_l at this thread's frequencies (kx = q + A e)
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < B; ++e) E[e * RS + q * TC + j] = v[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
+  __syncthreads();
+  // s at each frequency, then this group's component of the projection
+#pragma unroll
+  for (int e = 0; e < B; ++e) {
+    const int pos = e * RS + q * TC + j;
+    cx<T> s = lds[pos] + lds[REG + pos] + lds[2 * REG + pos];
+    const int kx = q + A * e;
+    const bool nyq = nyq_yz || ((g.nx % 2 == 0) && kx == g.nx / 2);
+    const T xx = xi_x(e);
+    const T xi2 = xx * xx + xy * xy + xz * xz;
+    s = (nyq || xi2 == (T)0) ? cx<T>{0, 0} : s * (post / xi2);
+    v[e] = s * (l == 0 ? xx : (l == 1 ? xy : xz));
+  }
+  if (ok && ky == 0 && kz == 0 && q == 0) {  // xi = 0: eq. (22) keeps stress-controlled components
+    v[0] = ((pp.mask >> comp) & 1u) ? cx<T>{(a0.re - (T)pp.off[comp]) * post, a0.im * post} : cx<T>{0, 0};
+  }
+  __syncthreads();
+  four_step_second_inv<A, B, +1>(v, q, tw, [&](int c, int a, cx<T> z) { E[c * RS + a * TC + j] = z; });
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B; ++b) v[b] = E[b * RS + q * TC + j];
+  dft<B, +1>(v);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < B; ++e) H[cbase + (long long)(q + A * e) * rs] = v[e];
+  }
+}
+
+// Variant "rows": one thread transforms all three components of its columns in turn and
+// carries only the scalar s between the forward and the inverse transforms.
 template <typename T, int A, int B>
 __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-XPROJ_ATTR xproj_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
+xproj_rows_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
              const CGScalars* __restrict__ sc) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
-  __shared__ cx<T> lds[A * B * TC];
+  constexpr int RS = Cfg::RS;
+  __shared__ cx<T> lds[Cfg::LDS];
   if (sc && sc->done) return;
   const int j = threadIdx.x % TC;
   const int q = threadIdx.x / TC;
@@ -255,7 +355,7 @@ XPROJ_ATTR xproj_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ 
   cx<T> a0[3];
 #pragma unroll
   for (int e = 0; e < B; ++e) s[e] = cx<T>{0, 0};
-GHOM_PRAGMA(XPROJ_UNROLL)
+#pragma nounroll
   for (int l = 0; l < 3; ++l) {
     const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + col;
     cx<T> v[B];
@@ -264,9 +364,9 @@ GHOM_PRAGMA(XPROJ_UNROLL)
     four_step_first<A, B, -1>(v, q, tw);
     if (l) __syncthreads();
 #pragma unroll
-    for (int c = 0; c < B; ++c) lds[(c * A + q) * TC + j] = v[c];
+    for (int c = 0; c < B; ++c) lds[c * RS + q * TC + j] = v[c];
     __syncthreads();
-    four_step_second<A, B, -1>(v, q, [&](int c, int a) { return lds[(c * A + a) * TC + j]; });
+    four_step_second<A, B, -1>(v, q, [&](int c, int a) { return lds[c * RS + a * TC + j]; });
 #pragma unroll
     for (int e = 0; e < B; ++e) s[e] = s[e] + v[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
     a0[l] = v[0];
@@ -279,7 +379,7 @@ GHOM_PRAGMA(XPROJ_UNROLL)
     const T xi2 = xx * xx + xy * xy + xz * xz;
     s[e] = (nyq || xi2 == (T)0) ? cx<T>{0, 0} : s[e] * (post / xi2);
   }
-GHOM_PRAGMA(XPROJ_UNROLL)
+#pragma nounroll
   for (int l = 0; l < 3; ++l) {
     cx<T> v[B];
 #pragma unroll
@@ -289,10 +389,10 @@ GHOM_PRAGMA(XPROJ_UNROLL)
       v[0] = ((pp.mask >> c) & 1u) ? cx<T>{(a0[l].re - (T)pp.off[c]) * post, a0[l].im * post} : cx<T>{0, 0};
     }
     __syncthreads();
-    four_step_second_inv<A, B, +1>(v, q, tw, [&](int c, int a, cx<T> z) { lds[(c * A + a) * TC + j] = z; });
+    four_step_second_inv<A, B, +1>(v, q, tw, [&](int c, int a, cx<T> z) { lds[c * RS + a * TC + j] = z; });
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < B; ++b) v[b] = lds[(b * A + q) * TC + j];
+    for (int b = 0; b < B; ++b) v[b] = lds[b * RS + q * TC + j];
     dft<B, +1>(v);
     if (ok) {
       cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + col;
@@ -330,7 +430,7 @@ __device__ __forceinline__ void tangent_nh(const T* st, const T* d, T* out) {
 
 // Saint Venant-Kirchhoff: K:dF = dF S + F (s C : sym(F^T dF)), C in 6x6 Voigt form
 template <typename T>
-__device__ __forceinline__ void tangent_svk(const T* st, const double* __restrict__ C6, const T* d, T* out) {
+__device__ __forceinline__ void tangent_svk(const T* st, const T* __restrict__ C6, const T* d, T* out) {
   const T* F = st;
   const T* S = st + 9;  // 11 22 33 23 13 12
   const T s = st[15];
@@ -348,7 +448,7 @@ __device__ __forceinline__ void tangent_svk(const T* st, const double* __restric
   for (int I = 0; I < 6; ++I) {
     T acc = 0;
 #pragma unroll
-    for (int J = 0; J < 6; ++J) acc += (T)C6[6 * I + J] * E[J];
+    for (int J = 0; J < 6; ++J) acc += C6[6 * I + J] * E[J];
     dS[I] = s * acc;
   }
   const T Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
@@ -377,7 +477,7 @@ struct ZfwdArgs {
   int update_p;               // nonzero: p <- r + beta p before use
   const T* state;             // tangent state planes
   const uint16_t* phase;      // SVK: phase of each voxel
-  const double* C6;           // SVK: per-phase 6x6 Voigt stiffness
+  const T* C6;                // SVK: per-phase 6x6 Voigt stiffness in the CG type
   int has_scale;              // SVK: state plane 15 holds s(x) (else s = 1)
   double* partials;           // nullable: per-block partial of sum p : (K : p) (FP64)
   cx<T>* H;                   // spectrum out
@@ -389,8 +489,8 @@ template <typename T, int A, int B, int MODE, typename TIN>
 __global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
 zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
   using Cfg = ZCfg<T, A, B>;
-  constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B;
-  __shared__ cx<T> lds[9 * LP * NZ];
+  constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
+  __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
@@ -442,32 +542,40 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
     }
     const int pair = lp >> 1, part = lp & 1;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * NZ + z) + part] = val[c];
+    for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * R + z) + part] = val[c];
   }
   __syncthreads();
   // phase 2: 9*LP complex transforms of length NZ (A threads each)
-  const int f = threadIdx.x / A, q = threadIdx.x - (threadIdx.x / A) * A;
-  cx<T>* L = lds + f * NZ;
+  constexpr int DIRZ = -1;
+  const bool ft = threadIdx.x < Cfg::NF;
+  const int f = ft ? threadIdx.x / A : 0, q = threadIdx.x - (threadIdx.x / A) * A;
+  cx<T>* L = lds + f * R;
   cx<T> v[B];
+  if (ft) {
 #pragma unroll
-  for (int b = 0; b < B; ++b) v[b] = L[q + A * b];
-  four_step_first<A, B, -1>(v, q, args.tw);
+    for (int b = 0; b < B; ++b) v[b] = L[q + A * b];
+    four_step_first<A, B, DIRZ>(v, q, args.tw);
+  }
   __syncthreads();
+  if (ft) {
 #pragma unroll
-  for (int c = 0; c < B; ++c) L[c * A + q] = v[c];
+    for (int c = 0; c < B; ++c) L[c * (A + 1) + q] = v[c];
+  }
   __syncthreads();
-  four_step_second<A, B, -1>(v, q, [&](int c, int a) { return L[c * A + a]; });
+  if (ft) four_step_second<A, B, DIRZ>(v, q, [&](int c, int a) { return L[c * (A + 1) + a]; });
   __syncthreads();
+  if (ft) {
 #pragma unroll
-  for (int e = 0; e < B; ++e) L[q + A * e] = v[e];
+    for (int e = 0; e < B; ++e) L[q + A * e] = v[e];
+  }
   __syncthreads();
   // phase 3: split the two real lines' spectra, store kz < nzh
   const int nzh = g.nzh;
   for (int t = threadIdx.x; t < 9 * LP * nzh; t += NT) {
     const int ff = t / nzh, kz = t - ff * nzh;
     const int c = ff / LP, pair = ff - c * LP;
-    const cx<T> Zk = lds[ff * NZ + kz];
-    const cx<T> Zm = conj(lds[ff * NZ + (kz == 0 ? 0 : NZ - kz)]);
+    const cx<T> Zk = lds[ff * R + kz];
+    const cx<T> Zm = conj(lds[ff * R + (kz == 0 ? 0 : NZ - kz)]);
     const cx<T> Ak = (Zk + Zm) * (T)0.5;
     const cx<T> Bk = mul_i<-1>(Zk - Zm) * (T)0.5;
     const long long l0 = line0 + 2 * pair;
@@ -500,8 +608,8 @@ template <typename T, int A, int B, typename TOUT, bool CGU>
 __global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
 zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
   using Cfg = ZCfg<T, A, B>;
-  constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B;
-  __shared__ cx<T> lds[9 * LP * NZ];
+  constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
+  __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
@@ -514,25 +622,33 @@ zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
     const long long l0 = line0 + 2 * pair;
     const cx<T> a = l0 < nlines ? args.H[c * g.Nh + l0 * nzh + kz] : cx<T>{0, 0};
     const cx<T> b = l0 + 1 < nlines ? args.H[c * g.Nh + (l0 + 1) * nzh + kz] : cx<T>{0, 0};
-    lds[ff * NZ + kz] = a + mul_i<+1>(b);
-    if (kz > 0) lds[ff * NZ + NZ - kz] = conj(a) + mul_i<+1>(conj(b));
-    if ((NZ % 2 == 0) && kz == 0) lds[ff * NZ + NZ / 2] = cx<T>{0, 0};
+    lds[ff * R + kz] = a + mul_i<+1>(b);
+    if (kz > 0) lds[ff * R + NZ - kz] = conj(a) + mul_i<+1>(conj(b));
+    if ((NZ % 2 == 0) && kz == 0) lds[ff * R + NZ / 2] = cx<T>{0, 0};
   }
   __syncthreads();
-  const int f = threadIdx.x / A, q = threadIdx.x - (threadIdx.x / A) * A;
-  cx<T>* L = lds + f * NZ;
+  constexpr int DIRZ = +1;
+  const bool ft = threadIdx.x < Cfg::NF;
+  const int f = ft ? threadIdx.x / A : 0, q = threadIdx.x - (threadIdx.x / A) * A;
+  cx<T>* L = lds + f * R;
   cx<T> v[B];
+  if (ft) {
 #pragma unroll
-  for (int b = 0; b < B; ++b) v[b] = L[q + A * b];
-  four_step_first<A, B, +1>(v, q, args.tw);
+    for (int b = 0; b < B; ++b) v[b] = L[q + A * b];
+    four_step_first<A, B, DIRZ>(v, q, args.tw);
+  }
   __syncthreads();
+  if (ft) {
 #pragma unroll
-  for (int c = 0; c < B; ++c) L[c * A + q] = v[c];
+    for (int c = 0; c < B; ++c) L[c * (A + 1) + q] = v[c];
+  }
   __syncthreads();
-  four_step_second<A, B, +1>(v, q, [&](int c, int a) { return L[c * A + a]; });
+  if (ft) four_step_second<A, B, DIRZ>(v, q, [&](int c, int a) { return L[c * (A + 1) + a]; });
   __syncthreads();
+  if (ft) {
 #pragma unroll
-  for (int e = 0; e < B; ++e) L[q + A * e] = v[e];
+    for (int e = 0; e < B; ++e) L[q + A * e] = v[e];
+  }
   __syncthreads();
   // phase 3: real lines out
   const T* ldsr = reinterpret_cast<const T*>(lds);
@@ -546,7 +662,7 @@ zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
     const int pair = lp >> 1, part = lp & 1;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * NZ + z) + part];
+      const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
       const long long i = c * g.N + vox;
       if constexpr (CGU) {
         const TOUT xv = args.x[i] + alpha * args.p[i];

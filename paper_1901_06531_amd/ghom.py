@@ -19,6 +19,8 @@ FP64 = 0
 FP32_SPLIT = 1
 FIELD_F = 0
 FIELD_P = 1
+OPT_XPROJ_F64 = 1
+OPT_XPROJ_F32 = 2
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
           -6: "EDOMAIN", -7: "ESTATE"}
@@ -66,6 +68,8 @@ _SIGS = {
     "ghom_apply_operator": (_i, [_vp, _vp, _vp]),
     "ghom_apply_projection": (_i, [_vp, _vp, _vp]),
     "ghom_residual": (_i, [_vp, _vp, _vp]),
+    "ghom_set_option": (_i, [_vp, _i, _i]),
+    "ghom_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
     "ghom_set_profiling": (_i, [_vp, _i]),
     "ghom_profile_count": (_i, [_vp]),
     "ghom_profile_get": (_i, [_vp, _i, ctypes.c_char_p, _i, ctypes.POINTER(_i), _dp]),
@@ -269,6 +273,15 @@ class Solver:
         _torch_sync()
         self._check(lib().ghom_residual(self._c, _ptr(Pb), _dev_ptr(out)))
         return out
+
+    # -- kernel options ------------------------------------------------------------------
+    def set_option(self, key, value):
+        self._check(lib().ghom_set_option(self._c, int(key), int(value)))
+
+    def get_option(self, key):
+        v = ctypes.c_int()
+        self._check(lib().ghom_get_option(self._c, int(key), ctypes.byref(v)))
+        return v.value
 
     # -- profiling -----------------------------------------------------------------------
     def set_profiling(self, on=True):

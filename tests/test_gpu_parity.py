@@ -44,14 +44,20 @@ def random_F(shape, g, amp=0.1):
     return np.ascontiguousarray(F)
 
 
+XPROJ = [1, 2]  # the two x-pass variants ("rows", "groups")
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("mask", ["stress", "strain", "mixed"])
-def test_projection_matches_oracle(shape, mask):
-    say("projection", shape, mask)
+@pytest.mark.parametrize("xproj", XPROJ)
+def test_projection_matches_oracle(shape, mask, xproj):
+    say("projection", shape, mask, "xproj variant", xproj)
     g = np.random.default_rng(1)
     A = g.standard_normal((9,) + shape)
     lengths = (1.0, 1.5, 0.75)
     with ghom.Solver(shape, lengths) as s:
+        assert s.get_option(ghom.OPT_XPROJ_F64) in (1, 2)  # tuned at creation
+        s.set_option(ghom.OPT_XPROJ_F64, xproj)
         s.set_control(MASKS[mask])
         out = s.apply_projection(dev(A)).cpu().numpy()
     ref = go.apply_projection(A, MASKS[mask], lengths)
@@ -74,12 +80,14 @@ def _svk_tables(n, seed):
 @pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 32), (48, 48, 48), (9, 27, 12), (64, 64, 64)])
 @pytest.mark.parametrize("law", ["nh", "svk"])
 @pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
-def test_operator_matches_oracle(shape, law, prec):
-    say("operator", shape, law, prec)
+@pytest.mark.parametrize("xproj", XPROJ)
+def test_operator_matches_oracle(shape, law, prec, xproj):
+    say("operator", shape, law, prec, "xproj variant", xproj)
     g = np.random.default_rng(2)
     F = random_F(shape, g)
     o = go.Oracle(shape)
     with ghom.Solver(shape, precision=prec) as s:
+        s.set_option(ghom.OPT_XPROJ_F64 if prec == ghom.FP64 else ghom.OPT_XPROJ_F32, xproj)
         if law == "nh":
             phase, mu, lam, scale = _nh_setup(shape, g)
             s.set_material_neohookean(phase, mu, lam)
