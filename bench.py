@@ -38,8 +38,9 @@ def op_bytes(name, N, Nh, w, svk=True, update_p=True):
         return 2 * spec
     if "zfwd" in name:
         state = (15 if svk else 12) * N * w + (2 * N if svk else 0)  # SVK: F, S (no scale plane)
+        # CG step: r, p in, p out (p = r + beta p folded in)
         return field * (3 if update_p else 1) + state + spec
-    if "zinv" in name:  # CG step: spectrum in; x, r, p in; x, r out
+    if "zinv" in name:  # CG step: spectrum, x, r, p in; x, r out
         return spec + 5 * field
     return None
 

@@ -166,7 +166,8 @@ int ghom_residual(ghom_ctx *ctx, const double Pbar[9], double *out_dev);
 /* Keys of ghom_set_option / ghom_get_option. */
 enum {
   GHOM_OPT_XPROJ_F64 = 1,  /* x-pass (transform along x + projection) variant, float64    */
-  GHOM_OPT_XPROJ_F32 = 2   /* the same for the float32 transforms of GHOM_FP32_SPLIT      */
+  GHOM_OPT_XPROJ_F32 = 2,  /* the same for the float32 transforms of GHOM_FP32_SPLIT      */
+  GHOM_OPT_ZSLABS = 3      /* number of kz slabs the y and x passes are run in (>= 1)     */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the faster variant by timing
@@ -174,6 +175,10 @@ enum {
  * thread transforms the three components of a tensor row in turn), 2 = "groups" (three
  * thread groups, one per component, meeting in LDS).  Both compute the same operator. */
 int ghom_set_option(ghom_ctx *ctx, int key, int value);
+
+/* GHOM_OPT_ZSLABS: the y-forward, x (projection) and y-inverse passes are run slab by slab
+ * over ranges of kz planes, so that a slab's intermediate spectrum can stay in the GPU's
+ * last-level cache between the three passes (1 = one launch per pass). */
 
 /* Reads the current value of an option (for the x-pass keys: the variant in use, 1 or 2,
  * once tuned). */

@@ -80,6 +80,8 @@ struct ghom_ctx {
   std::string err;
   // x-pass variant per precision ([0] float64, [1] float32): 0 untuned, 1 rows, 2 groups
   int xproj_var[2] = {0, 0};
+  // kz slabs of the middle passes (1 = whole spectrum per pass)
+  int zslabs = 1;
   // profiling
   bool prof = false;
   std::map<std::string, ProfRec> prof_recs;
@@ -216,14 +218,14 @@ int launch_zinv(ghom_ctx* c, const ZinvArgs<T, TOUT>& a, const char* name) {
 }
 
 template <typename T, int DIR>
-void launch_ypass(ghom_ctx* c, const CGScalars* sc, const char* name) {
+void launch_ypass(ghom_ctx* c, Slab sl, const CGScalars* sc, const char* name) {
   with_split(c->g.ny, [&](auto s) {
     using S = decltype(s);
     using Cfg = ColCfg<T, S::A, S::B>;
-    const long long ncols = 9LL * c->g.nx * c->g.nzh;
+    const long long ncols = 9LL * c->g.nx * sl.nkz;
     const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
     timed(c, name, [&] {
-      hipLaunchKernelGGL((ypass_kernel<T, S::A, S::B, DIR>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g,
+      hipLaunchKernelGGL((ypass_kernel<T, S::A, S::B, DIR>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g, sl,
                          reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 1), sc);
     });
   });
@@ -234,28 +236,43 @@ enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2 };
 template <typename T> int& xproj_choice(ghom_ctx* c) { return c->xproj_var[sizeof(T) == 8 ? 0 : 1]; }
 
 template <typename T>
-void launch_xproj_variant(ghom_ctx* c, int variant, const ProjParams& pp, const CGScalars* sc) {
+void launch_xproj_variant(ghom_ctx* c, int variant, Slab sl, const ProjParams& pp, const CGScalars* sc) {
   with_split(c->g.nx, [&](auto s) {
     using S = decltype(s);
-    const long long ncols = (long long)c->g.ny * c->g.nzh;
+    const long long ncols = (long long)c->g.ny * sl.nkz;
     if (variant == XPROJ_ROWS) {
       using Cfg = ColCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      hipLaunchKernelGGL((xproj_rows_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g,
+      hipLaunchKernelGGL((xproj_rows_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g, sl,
                          reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 0), pp, sc);
     } else {
       using Cfg = XCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      hipLaunchKernelGGL((xproj_groups_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g,
+      hipLaunchKernelGGL((xproj_groups_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g, sl,
                          reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 0), pp, sc);
     }
   });
 }
 
 template <typename T>
-void launch_xproj(ghom_ctx* c, const ProjParams& pp, const CGScalars* sc, const char* name) {
+void launch_xproj(ghom_ctx* c, Slab sl, const ProjParams& pp, const CGScalars* sc, const char* name) {
   const int v = xproj_choice<T>(c);
-  timed(c, name, [&] { launch_xproj_variant<T>(c, v == XPROJ_TUNED ? XPROJ_ROWS : v, pp, sc); });
+  timed(c, name, [&] { launch_xproj_variant<T>(c, v == XPROJ_TUNED ? XPROJ_ROWS : v, sl, pp, sc); });
+}
+
+// The three middle passes (y forward, x with the projection, y inverse), kz-slab by slab.
+template <typename T>
+void middle_passes(ghom_ctx* c, const ProjParams& pp, const CGScalars* sc, const std::string& pre) {
+  const std::string t = tname<T>();
+  const std::string n2 = pre + "yfwd_" + t, n3 = pre + "xproj_" + t, n4 = pre + "yinv_" + t;
+  const int ns = std::max(1, std::min(c->zslabs, c->g.nzh));
+  const int per = (c->g.nzh + ns - 1) / ns;
+  for (int kz0 = 0; kz0 < c->g.nzh; kz0 += per) {
+    const Slab sl{kz0, std::min(per, c->g.nzh - kz0)};
+    launch_ypass<T, -1>(c, sl, sc, n2.c_str());
+    launch_xproj<T>(c, sl, pp, sc, n3.c_str());
+    launch_ypass<T, +1>(c, sl, sc, n4.c_str());
+  }
 }
 
 // Autotuner: times both x-pass variants on the (scratch) spectrum buffer with HIP events
@@ -269,12 +286,13 @@ void tune_xproj(ghom_ctx* c) {
   float best = 0.f;
   int best_v = XPROJ_ROWS;
   for (int v : {XPROJ_ROWS, XPROJ_GROUPS}) {
-    launch_xproj_variant<T>(c, v, pp, nullptr);  // warm-up
+    const Slab full{0, c->g.nzh};
+    launch_xproj_variant<T>(c, v, full, pp, nullptr);  // warm-up
     HIPCALL(hipGetLastError());
     float tmin = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
       HIPCALL(hipEventRecord(e0, c->stream));
-      launch_xproj_variant<T>(c, v, pp, nullptr);
+      launch_xproj_variant<T>(c, v, full, pp, nullptr);
       HIPCALL(hipGetLastError());
       HIPCALL(hipEventRecord(e1, c->stream));
       HIPCALL(hipEventSynchronize(e1));
@@ -314,9 +332,7 @@ int project64(ghom_ctx* c, const TIN* in, double* out, double scale, const doubl
               n3 = std::string(tag) + "_xproj_f64", n4 = std::string(tag) + "_yinv_f64",
               n5 = std::string(tag) + "_zinv_f64";
   launch_zfwd<double, Z_PLAIN, TIN>(c, za, n1.c_str());
-  launch_ypass<double, -1>(c, nullptr, n2.c_str());
-  launch_xproj<double>(c, make_proj(c, scale, Pbar), nullptr, n3.c_str());
-  launch_ypass<double, +1>(c, nullptr, n4.c_str());
+  middle_passes<double>(c, make_proj(c, scale, Pbar), nullptr, std::string(tag) + "_");
   ZinvArgs<double, double> zi{};
   zi.H = reinterpret_cast<cx<double>*>(c->H);
   zi.out = out;
@@ -357,9 +373,7 @@ void operator_apply(ghom_ctx* c, T* v, T* Av, bool cg, bool update_p, const CGSc
       hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gz, 1);
     });
   }
-  launch_ypass<T, -1>(c, sc, n2.c_str());
-  launch_xproj<T>(c, make_proj(c, 1.0, nullptr), sc, n3.c_str());
-  launch_ypass<T, +1>(c, sc, n4.c_str());
+  middle_passes<T>(c, make_proj(c, 1.0, nullptr), sc, "op_");
   ZinvArgs<T, T> zi{};
   zi.H = reinterpret_cast<cx<T>*>(c->H);
   zi.partials = c->partials;
@@ -1038,6 +1052,11 @@ int ghom_set_option(ghom_ctx* c, int key, int value) {
       }
       return GHOM_OK;
     }
+    if (key == GHOM_OPT_ZSLABS) {
+      if (value < 1 || value > 4096) fail(GHOM_EINVAL, "slab count must be in [1, 4096]");
+      c->zslabs = value;
+      return GHOM_OK;
+    }
     fail(GHOM_EINVAL, "unknown option");
   });
 }
@@ -1047,6 +1066,7 @@ int ghom_get_option(ghom_ctx* c, int key, int* value) {
     if (!value) fail(GHOM_EINVAL, "null output");
     if (key == GHOM_OPT_XPROJ_F64) *value = c->xproj_var[0];
     else if (key == GHOM_OPT_XPROJ_F32) *value = c->xproj_var[1];
+    else if (key == GHOM_OPT_ZSLABS) *value = c->zslabs;
     else fail(GHOM_EINVAL, "unknown option");
     return GHOM_OK;
   });

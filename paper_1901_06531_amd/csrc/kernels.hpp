@@ -31,6 +31,12 @@ struct Geo {
   double invL[3];
 };
 
+// A range of kz planes of the spectrum: the y and x passes can run slab by slab so that
+// the slab's intermediate results stay in the on-chip caches between the passes.
+struct Slab {
+  int kz0, nkz;
+};
+
 enum { MAT_NH = 1, MAT_SVK = 2 };
 constexpr int kNHState = 12;   // F^-T (9), a = s mu, b = s lam, c = s (mu - lam ln J)
 constexpr int kSVKState = 16;  // F (9), S in Voigt order 11 22 33 23 13 12 (6), s (1)
@@ -187,7 +193,7 @@ __device__ __forceinline__ void four_step_second_inv(const cx<T>* v, int q, cons
 // ---------------------------------------------------------------------------------
 template <typename T, int A, int B, int DIR>
 __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-ypass_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const CGScalars* __restrict__ sc) {
+ypass_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const CGScalars* __restrict__ sc) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -195,11 +201,11 @@ ypass_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const C
   if (sc && sc->done) return;
   const int j = threadIdx.x % TC;
   const int q = threadIdx.x / TC;
-  const long long ncols = 9LL * g.nx * g.nzh;
+  const long long ncols = 9LL * g.nx * sl.nkz;
   const long long col = (long long)blockIdx.x * TC + j;
   const bool ok = col < ncols;
-  const long long grp = col / g.nzh;  // (c, x)
-  const long long base = grp * ((long long)g.ny * g.nzh) + (col - grp * g.nzh);
+  const long long grp = col / sl.nkz;  // (c, x)
+  const long long base = grp * ((long long)g.ny * g.nzh) + sl.kz0 + (col - grp * sl.nkz);
   const long long rs = g.nzh;
   cx<T> v[B];
 #pragma unroll
@@ -257,7 +263,7 @@ template <typename T, int A, int B> struct XCfg {
 
 template <typename T, int A, int B>
 __global__ void __launch_bounds__((XCfg<T, A, B>::NT))
-xproj_groups_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
+xproj_groups_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
              const CGScalars* __restrict__ sc) {
   using Cfg = XCfg<T, A, B>;
   constexpr int TC = Cfg::TC, RS = Cfg::RS, REG = Cfg::REG;
@@ -270,18 +276,19 @@ xproj_groups_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, 
   const int row = blockIdx.y;
   const int comp = 3 * row + l;
   cx<T>* E = lds + l * REG;                     // this group's exchange region
-  const long long ncols = (long long)g.ny * g.nzh;
-  const long long col = (long long)blockIdx.x * TC + j;
+  const long long ncols = (long long)g.ny * sl.nkz;
+  const long long col = (long long)blockIdx.x * TC + j;  // column (ky, kz - kz0) of the slab
   const bool ok = col < ncols;
-  const long long rs = ncols;
-  const int ky = ok ? (int)(col / g.nzh) : 0;
-  const int kz = ok ? (int)(col - (long long)ky * g.nzh) : 0;
+  const long long rs = (long long)g.ny * g.nzh;  // stride between x rows
+  const int ky = ok ? (int)(col / sl.nkz) : 0;
+  const int kz = ok ? sl.kz0 + (int)(col - (long long)ky * sl.nkz) : 0;
+  const long long gcol = (long long)ky * g.nzh + kz;  // column (ky, kz) of the spectrum plane
   const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
   const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
   const T xz = (T)(kz * g.invL[2]);
   const T post = (T)pp.post;
   auto xi_x = [&](int e) { return (T)(signed_k(q + A * e, g.nx) * g.invL[0]); };
-  const long long cbase = (long long)comp * g.Nh + col;
+  const long long cbase = (long long)comp * g.Nh + gcol;
   cx<T> v[B];
 #pragma unroll
   for (int e = 0; e < B; ++e) v[e] = ok ? H[cbase + (long long)(q + A * e) * rs] : cx<T>{0, 0};
@@ -328,7 +335,7 @@ xproj_groups_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, 
 // carries only the scalar s between the forward and the inverse transforms.
 template <typename T, int A, int B>
 __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-xproj_rows_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
+xproj_rows_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
              const CGScalars* __restrict__ sc) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
@@ -338,12 +345,13 @@ xproj_rows_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, Pr
   const int j = threadIdx.x % TC;
   const int q = threadIdx.x / TC;
   const int row = blockIdx.y;  // tensor row i: components 3i, 3i+1, 3i+2
-  const long long ncols = (long long)g.ny * g.nzh;
-  const long long col = (long long)blockIdx.x * TC + j;
+  const long long ncols = (long long)g.ny * sl.nkz;
+  const long long col = (long long)blockIdx.x * TC + j;  // column (ky, kz - kz0) of the slab
   const bool ok = col < ncols;
-  const long long rs = ncols;
-  const int ky = ok ? (int)(col / g.nzh) : 0;
-  const int kz = ok ? (int)(col - (long long)ky * g.nzh) : 0;
+  const long long rs = (long long)g.ny * g.nzh;  // stride between x rows
+  const int ky = ok ? (int)(col / sl.nkz) : 0;
+  const int kz = ok ? sl.kz0 + (int)(col - (long long)ky * sl.nkz) : 0;
+  const long long gcol = (long long)ky * g.nzh + kz;  // column (ky, kz) of the spectrum plane
   const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
   const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
   const T xz = (T)(kz * g.invL[2]);
@@ -357,7 +365,7 @@ xproj_rows_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, Pr
   for (int e = 0; e < B; ++e) s[e] = cx<T>{0, 0};
 #pragma nounroll
   for (int l = 0; l < 3; ++l) {
-    const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + col;
+    const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + gcol;
     cx<T> v[B];
 #pragma unroll
     for (int e = 0; e < B; ++e) v[e] = ok ? src[(long long)(q + A * e) * rs] : cx<T>{0, 0};
@@ -395,7 +403,7 @@ xproj_rows_kernel(Geo g, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, Pr
     for (int b = 0; b < B; ++b) v[b] = lds[b * RS + q * TC + j];
     dft<B, +1>(v);
     if (ok) {
-      cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + col;
+      cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + gcol;
 #pragma unroll
       for (int e = 0; e < B; ++e) dst[(long long)(q + A * e) * rs] = v[e];
     }
@@ -472,7 +480,7 @@ enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2 };
 template <typename T, typename TIN>
 struct ZfwdArgs {
   const TIN* in;              // Z_PLAIN: field to transform (9 planes)
-  T* p;                       // Z_NH/Z_SVK: CG direction (updated in place when beta != 0)
+  T* p;                       // Z_NH/Z_SVK: CG direction (updated in place when update_p)
   const T* r;                 // CG residual for p <- r + beta p
   int update_p;               // nonzero: p <- r + beta p before use
   const T* state;             // tangent state planes
@@ -515,8 +523,9 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
         if (args.update_p) {
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            d[c] = args.r[c * g.N + vox] + beta * d[c];
-            args.p[c * g.N + vox] = d[c];
+            const long long i = c * g.N + vox;
+            d[c] = args.r[i] + beta * d[c];
+            args.p[i] = d[c];
           }
         }
         if constexpr (MODE == Z_NH) {

@@ -21,6 +21,7 @@ FIELD_F = 0
 FIELD_P = 1
 OPT_XPROJ_F64 = 1
 OPT_XPROJ_F32 = 2
+OPT_ZSLABS = 3
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
           -6: "EDOMAIN", -7: "ESTATE"}
