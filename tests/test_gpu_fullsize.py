@@ -1,0 +1,155 @@
+"""Parity at the benchmark sizes (256^3 polycrystal, 128^3 particle and adjoint cells).
+
+The oracle cannot run Newton to convergence at these sizes in reasonable time, so:
+  * the operator A(v) = G*(K : v) is compared element by element at 256^3 (one oracle
+    application, in the precision and kernel variant the benchmark uses);
+  * converged GPU states are checked against the oracle's own equilibrium equations: the
+    oracle's residual -G*(P(F) - P-bar) evaluated at the GPU's F must be at the CG
+    tolerance, and the GPU's FP64 residual must agree with it element by element;
+  * invariants that hold at any size: prescribed components met, Hill-Mandel;
+  * the adjoint gradient at 128^3 against central finite differences of re-solved states.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ghom_oracle as go  # noqa: E402
+from paper_1901_06531_amd import ghom, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _oracle_for(w):
+    o = go.Oracle(w["shape"])
+    if w["kind"] == "nh":
+        o.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+    else:
+        o.set_material_svk(w["phase"], w["C"])
+    if w.get("scale") is not None:
+        o.set_stiffness_scale(w["scale"])
+    o.set_control(w["mask"])
+    o.set_history(w["target"])
+    return o
+
+
+@pytest.fixture(scope="module")
+def poly256():
+    say("building the 256^3 polycrystal workload")
+    return synth.workload_polycrystal(n=256)
+
+
+def test_polycrystal256_operator_matches_oracle(poly256):
+    w = poly256
+    g = np.random.default_rng(11)
+    F = np.broadcast_to(np.eye(3).reshape(9, 1, 1, 1), (9,) + w["shape"]) + 0.01 * g.standard_normal((9,) + w["shape"])
+    v = g.standard_normal((9,) + w["shape"])
+    say("oracle operator at 256^3")
+    o = _oracle_for(w)
+    ref = o.apply_operator(v, F)
+    scale = np.max(np.abs(ref))
+    for prec, dt, tol in [(ghom.FP32_SPLIT, torch.float32, 2e-5), (ghom.FP64, torch.float64, 1e-12)]:
+        say("gpu operator at 256^3, precision", prec)
+        with ghom.Solver(w["shape"], precision=prec) as s:
+            s.setup(w)
+            s.load_state(F, 0)
+            out = s.apply_operator(torch.from_numpy(v).to("cuda", dt)).double().cpu().numpy()
+        err = np.max(np.abs(out - ref)) / scale
+        say("  max rel err %.3e" % err)
+        assert err < tol
+        del out
+
+
+def _equilibrium_checks(w, s, tol_rms):
+    """The GPU's converged state against the oracle's equilibrium equations."""
+    F = s.field(ghom.FIELD_F)
+    Favg, Pavg = s.averages()
+    o = _oracle_for(w)
+    o.set_state(F, 1)
+    Pbar = o.target_stress(1)
+    say("oracle stress and residual at the GPU state")
+    P = o.stress(F)
+    b = o.residual(P, Pbar)
+    rms = o.rms(b)
+    say("  oracle residual rms %.3e" % rms)
+    assert rms < tol_rms
+    b_gpu = s.residual(Pbar).cpu().numpy()
+    assert np.max(np.abs(b_gpu - b)) < 1e-12 * max(1.0, np.max(np.abs(P)))
+    mask = np.asarray(w["mask"]) > 0
+    fmask = ~mask
+    np.testing.assert_allclose(Pavg[mask], Pbar[mask], rtol=0, atol=10 * tol_rms)
+    np.testing.assert_allclose(Favg[fmask], w["target"][0][fmask], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(Pavg, P.reshape(9, -1).mean(axis=1), rtol=0, atol=1e-13)
+    hm = float(np.mean(np.sum(P * F, axis=0)))
+    assert abs(hm - float(Pavg @ Favg)) < 10 * tol_rms
+
+
+def test_polycrystal256_increment_satisfies_oracle_equilibrium(poly256):
+    """First load increment of the benchmark (FP32-split, paper tolerances)."""
+    w = poly256
+    with ghom.Solver(w["shape"], precision=ghom.FP32_SPLIT) as s:
+        s.setup(w)
+        info = s.step()
+        say("gpu increment 1: newton %d cg %d" % (info["newton_iters"], info["cg_iters_total"]))
+        _equilibrium_checks(w, s, tol_rms=1e-7)
+
+
+def test_particles128_mixed_increment_satisfies_oracle_equilibrium():
+    w = synth.workload_particles(n=128)
+    with ghom.Solver(w["shape"], precision=ghom.FP64) as s:
+        s.setup(w)
+        info = s.step()
+        say("gpu increment 1: newton %d cg %d" % (info["newton_iters"], info["cg_iters_total"]))
+        _equilibrium_checks(w, s, tol_rms=1e-7)
+
+
+def test_adjoint128_matches_finite_differences():
+    """dJ/ds for J = <F>_11 at the end of the 128^3 stress-controlled history, against
+    central differences of re-solved states: along a random direction (whole field) and at
+    100 random voxels (relative step 1e-2)."""
+    w = synth.workload_adjoint(n=128)
+    N = int(np.prod(w["shape"]))
+    s_field = w["scale"].reshape(-1).copy()
+    a = np.zeros(9)
+    a[0] = 1.0
+    with ghom.Solver(w["shape"], precision=ghom.FP64) as s:
+        s.setup(w)
+        s.set_tolerances(1e-12, 1e-12)
+        for k in range(len(w["target"])):
+            info = s.step()
+        say("history done: last increment newton %d cg %d" % (info["newton_iters"], info["cg_iters_total"]))
+        grad = s.adjoint_grad_scale(a).reshape(-1)
+        F0, k0 = s.save_state()
+
+        def J_at(sv):
+            s.set_stiffness_scale(sv)
+            s.load_state(F0, k0)
+            s.resolve()
+            return s.averages()[0][0]
+
+        g = np.random.default_rng(6)
+        d = synth.smooth_scale_field(w["shape"], 7, ell=0.1, lo=-1.0, hi=1.0).reshape(-1)
+        eps = 1e-4
+        Jp = J_at(s_field * (1 + eps * d))
+        Jm = J_at(s_field * (1 - eps * d))
+        fd_dir = (Jp - Jm) / 2.0
+        ad_dir = float(np.dot(grad, eps * d * s_field))
+        say("directional: fd %.6e adjoint %.6e" % (fd_dir, ad_dir))
+        assert abs(fd_dir - ad_dir) <= 1e-5 * abs(ad_dir)
+        worst = 0.0
+        for v in g.choice(N, 100, replace=False):
+            h = 1e-2 * s_field[v]
+            sp = s_field.copy()
+            sp[v] += h
+            Jp = J_at(sp)
+            sp[v] -= 2 * h
+            Jm = J_at(sp)
+            fd = (Jp - Jm) / (2 * h)
+            worst = max(worst, abs(fd - grad[v]) / abs(grad[v]))
+        say("100 voxels: worst relative difference %.3e" % worst)
+        assert worst < 1e-3
