@@ -201,6 +201,64 @@ int ghom_profile_get(ghom_ctx *ctx, int i, char *name_out, int name_cap, int *la
 /* Clears the timing records. */
 int ghom_profile_reset(ghom_ctx *ctx);
 
+/* ---- batches of independent problems ------------------------------------------------ */
+
+/* Many cells and load cases advanced together (e.g. a set of RVEs under several load
+ * paths).  Problems with the same grid and material law share every launch: each pass of
+ * the method is one kernel launch per such group, whatever the number of problems. */
+typedef struct ghom_batch ghom_batch;
+
+enum { GHOM_MATERIAL_NEOHOOKEAN = 1, GHOM_MATERIAL_SVK = 2 };
+
+/* One problem of a batch (host pointers, read by ghom_batch_create only).  The cell is the
+ * unit cube.  kind selects the material law of ghom_set_material_neohookean (mu, lambda:
+ * nphase values each) or ghom_set_material_svk (C: nphase x 81 values); phase has nx*ny*nz
+ * entries; mask and target (nsteps x 9) as in ghom_set_control / ghom_set_history. */
+typedef struct {
+  int nx, ny, nz;
+  int kind;
+  const uint16_t *phase;
+  int nphase;
+  const double *mu, *lambda;
+  const double *C;
+  uint8_t mask[9];
+  int nsteps;
+  const double *target;
+} ghom_problem;
+
+/* Creates a batch of nprob problems (1..65535) in one precision on one device; all device
+ * memory is allocated here.  hip_stream as in ghom_create. */
+int ghom_batch_create(ghom_batch **out, const ghom_problem *probs, int nprob, int precision, int device,
+                      void *hip_stream);
+
+/* Releases the batch (NULL is ignored). */
+void ghom_batch_destroy(ghom_batch *b);
+
+/* Message of the last failed call on b. */
+const char *ghom_batch_last_error(const ghom_batch *b);
+
+/* Stopping rules shared by every problem (see ghom_set_tolerances). */
+int ghom_batch_set_tolerances(ghom_batch *b, double newton_tol, double cg_tol, double cg_forcing,
+                              int max_newton, int max_cg);
+
+/* Advances every problem whose history is not exhausted by one increment.  info (nullable,
+ * host) receives nprob records; problems not advanced have status GHOM_ESTATE.  Returns
+ * GHOM_OK if every advanced problem converged, else the first failing problem's status
+ * (the others are still advanced). */
+int ghom_batch_step(ghom_batch *b, ghom_step_info *info);
+
+/* <F> and <P> of problem iprob (host, 9 values each). */
+int ghom_batch_get_averages(ghom_batch *b, int iprob, double Fbar[9], double Pbar[9]);
+
+/* Field of problem iprob to host memory (as ghom_get_field). */
+int ghom_batch_get_field(ghom_batch *b, int iprob, int which, double *host_out);
+
+/* Kernel options of the batch (as ghom_set_option). */
+int ghom_batch_set_option(ghom_batch *b, int key, int value);
+
+/* Number of launch groups (distinct grid and material law) of the batch. */
+int ghom_batch_num_classes(ghom_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,9 +1,15 @@
 // libghom.so: host runtime and C ABI (include/ghom.h) of the Galerkin-FFT solver with
 // stress / mixed control.  Every step of the method runs in the kernels of kernels.hpp on
-// the context's HIP stream; the host only sequences launches, moves a few scalars and
+// the stream of the engine; the host only sequences launches, moves a few scalars and
 // applies the stopping rules.
+//
+// An engine holds any number of independent problems.  Problems with the same grid and
+// material law form a shape class; every pass is one launch per class covering all of its
+// problems (blockIdx.z = problem), so a batch of hundreds of cells costs a handful of
+// launches per pass.  A ghom_ctx is an engine with one problem.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,84 +27,15 @@ namespace {
 
 constexpr int kMaxVoxBlocks = 8192;
 
-struct ProfRec {
-  int launches = 0;
-  double ms = 0.0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-};
-
-}  // namespace
-
-struct ghom_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int prec = GHOM_FP64;
-  Geo g{};
-  size_t tsz = 8;  // bytes of the CG type
-
-  // fields (FP64 master copies)
-  double* F = nullptr;
-  double* P = nullptr;
-  double* b = nullptr;
-  double* dF64 = nullptr;  // split mode: re-projected Newton correction
-  // CG vectors and tangent state in the CG type
-  void* x = nullptr;
-  void* r = nullptr;
-  void* p = nullptr;
-  void* state = nullptr;
-  void* H = nullptr;  // spectrum, FP64 capacity
-  // material
-  int kind = 0;
-  int nphase = 0;
-  uint16_t* phase = nullptr;
-  double* scale = nullptr;
-  double* mat = nullptr;  // NH: (mu, lam) per phase; SVK: 36 Voigt values per phase
-  float* mat32 = nullptr; // SVK: the Voigt table in float32 (tangent of the FP32 CG)
-  bool state_valid = false;
-  // twiddles W_n^k = exp(-2 pi i k / n) per axis
-  cx<double>* tw64[3] = {nullptr, nullptr, nullptr};
-  cx<float>* tw32[3] = {nullptr, nullptr, nullptr};
-  // reductions
-  double* partials = nullptr;
-  size_t npartials = 0;
-  CGScalars* sc = nullptr;
-  int* flag = nullptr;
-  double* red = nullptr;   // 32 reduced values
-  double* host_red = nullptr;  // pinned mirror
-  CGScalars* host_sc = nullptr;
-  // control / history
-  uint8_t mask[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  bool mask_set = false;
-  std::vector<double> target;
-  int nsteps = 0;
-  int k = 0;
-  double newton_tol = 1e-6, cg_tol = 1e-8, cg_forcing = 0.0;
-  int max_newton = 50, max_cg = 5000;
-  double Favg[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  double Pavg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  std::string err;
-  // x-pass variant per precision ([0] float64, [1] float32): 0 untuned, 1 rows, 2 groups
-  int xproj_var[2] = {0, 0};
-  // kz slabs of the middle passes (1 = whole spectrum per pass)
-  int zslabs = 1;
-  // profiling
-  bool prof = false;
-  std::map<std::string, ProfRec> prof_recs;
-  std::vector<hipEvent_t> ev_pool;
-};
-
-namespace {
-
 struct HipFail {
   hipError_t e;
   const char* what;
 };
 
-#define HIPCALL(expr)                          \
-  do {                                         \
-    hipError_t _e = (expr);                    \
-    if (_e != hipSuccess) throw HipFail{_e, #expr}; \
+#define HIPCALL(expr)                                 \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) throw HipFail{_e, #expr};   \
   } while (0)
 
 struct ApiError {
@@ -108,62 +45,135 @@ struct ApiError {
 
 [[noreturn]] void fail(int code, const std::string& msg) { throw ApiError{code, msg}; }
 
+struct ProfRec {
+  int launches = 0;
+  double ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2 };
+
+struct ShapeClass {
+  int nx = 0, ny = 0, nz = 0, kind = 0;
+  Geo g{};
+  std::vector<int> probs;  // problem indices
+  int* ids = nullptr;      // device copy of probs
+  cx<double>* tw64[3] = {nullptr, nullptr, nullptr};
+  cx<float>* tw32[3] = {nullptr, nullptr, nullptr};
+  int xproj_var[2] = {XPROJ_TUNED, XPROJ_TUNED};  // [0] float64, [1] float32
+  int vb = 1;                                     // voxel-kernel blocks per problem
+};
+
+struct Prob {
+  int cls = -1;
+  int kind = 0;
+  int nphase = 0;
+  uint8_t mask[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  bool mask_set = false;
+  std::vector<double> target;
+  int nsteps = 0;
+  int k = 0;
+  double Favg[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double Pavg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  bool state_valid = false;
+  // solve bookkeeping
+  bool running = false;
+  int status = GHOM_OK;
+  std::string msg;
+  double rms_b = 0.0;
+  ghom_step_info info{};
+  // device buffers owned outside the arena
+  double* scale = nullptr;
+  double* mat = nullptr;
+  float* mat32 = nullptr;
+};
+
+struct Engine {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int prec = GHOM_FP64;
+  size_t tsz = 8;
+  std::vector<Prob> P;
+  std::vector<ShapeClass> C;
+  ProbDesc* hdesc = nullptr;  // pinned host mirror
+  ProbDesc* ddesc = nullptr;
+  char* arena = nullptr;
+  size_t np = 0;              // partials per problem
+  CGScalars* sc = nullptr;    // device, one per problem
+  double* red = nullptr;      // device, 32 per problem
+  int* flags = nullptr;       // device, one per problem
+  CGScalars* host_sc = nullptr;
+  double* host_red = nullptr;
+  int* host_flags = nullptr;
+  double newton_tol = 1e-6, cg_tol = 1e-8, cg_forcing = 0.0;
+  int max_newton = 50, max_cg = 5000;
+  int zslabs = 1;
+  bool prof = false;
+  std::map<std::string, ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  std::string err;
+};
+
+// ------------------------------------------------------------------ plumbing ----------
 template <typename F>
-int guard(ghom_ctx* c, F&& f) {
-  if (!c) return GHOM_EINVAL;
+int guarded(Engine* e, F&& f) {
+  if (!e) return GHOM_EINVAL;
   try {
-    c->err.clear();
-    HIPCALL(hipSetDevice(c->device));
+    e->err.clear();
+    HIPCALL(hipSetDevice(e->device));
     return f();
-  } catch (const ApiError& e) {
-    c->err = e.msg;
-    return e.code;
-  } catch (const HipFail& e) {
-    c->err = std::string("HIP error '") + hipGetErrorString(e.e) + "' in " + e.what;
-    return e.e == hipErrorOutOfMemory ? GHOM_ENOMEM : GHOM_EHIP;
+  } catch (const ApiError& x) {
+    e->err = x.msg;
+    return x.code;
+  } catch (const HipFail& x) {
+    e->err = std::string("HIP error '") + hipGetErrorString(x.e) + "' in " + x.what;
+    return x.e == hipErrorOutOfMemory ? GHOM_ENOMEM : GHOM_EHIP;
   } catch (const std::bad_alloc&) {
-    c->err = "host allocation failed";
+    e->err = "host allocation failed";
     return GHOM_ENOMEM;
   }
 }
 
-hipEvent_t get_event(ghom_ctx* c) {
-  if (!c->ev_pool.empty()) {
-    hipEvent_t e = c->ev_pool.back();
-    c->ev_pool.pop_back();
-    return e;
+void sync(Engine& e) { HIPCALL(hipStreamSynchronize(e.stream)); }
+
+hipEvent_t get_event(Engine& e) {
+  if (!e.ev_pool.empty()) {
+    hipEvent_t ev = e.ev_pool.back();
+    e.ev_pool.pop_back();
+    return ev;
   }
-  hipEvent_t e;
-  HIPCALL(hipEventCreate(&e));
-  return e;
+  hipEvent_t ev;
+  HIPCALL(hipEventCreate(&ev));
+  return ev;
 }
 
-// Runs `launch` on the context stream, bracketed by events when profiling.
+// Runs `launch` on the engine stream, bracketed by events when profiling.
 template <typename L>
-void timed(ghom_ctx* c, const char* name, L&& launch) {
-  if (!c->prof) {
+void timed(Engine& e, const std::string& name, L&& launch) {
+  if (!e.prof) {
     launch();
     HIPCALL(hipGetLastError());
     return;
   }
-  hipEvent_t a = get_event(c), b = get_event(c);
-  HIPCALL(hipEventRecord(a, c->stream));
+  hipEvent_t a = get_event(e), b = get_event(e);
+  HIPCALL(hipEventRecord(a, e.stream));
   launch();
   HIPCALL(hipGetLastError());
-  HIPCALL(hipEventRecord(b, c->stream));
-  c->prof_recs[name].pending.emplace_back(a, b);
+  HIPCALL(hipEventRecord(b, e.stream));
+  e.prof_recs[name].pending.emplace_back(a, b);
 }
 
-void prof_collect(ghom_ctx* c) {
-  HIPCALL(hipStreamSynchronize(c->stream));
-  for (auto& kv : c->prof_recs) {
+void prof_collect(Engine& e) {
+  sync(e);
+  for (auto& kv : e.prof_recs) {
     for (auto& pr : kv.second.pending) {
       float ms = 0.f;
       HIPCALL(hipEventElapsedTime(&ms, pr.first, pr.second));
       kv.second.ms += ms;
       kv.second.launches += 1;
-      c->ev_pool.push_back(pr.first);
-      c->ev_pool.push_back(pr.second);
+      e.ev_pool.push_back(pr.first);
+      e.ev_pool.push_back(pr.second);
     }
     kv.second.pending.clear();
   }
@@ -173,128 +183,124 @@ template <typename T> const char* tname();
 template <> const char* tname<double>() { return "f64"; }
 template <> const char* tname<float>() { return "f32"; }
 
-template <typename T> const T* mat_table(ghom_ctx* c);
-template <> const double* mat_table<double>(ghom_ctx* c) { return c->mat; }
-template <> const float* mat_table<float>(ghom_ctx* c) { return c->mat32; }
-
-template <typename T> cx<T>* twid(ghom_ctx* c, int axis);
-template <> cx<double>* twid<double>(ghom_ctx* c, int axis) { return c->tw64[axis]; }
-template <> cx<float>* twid<float>(ghom_ctx* c, int axis) { return c->tw32[axis]; }
-
 int vox_blocks(long long n) {
-  long long b = (n + kVoxThreads - 1) / kVoxThreads;
-  return (int)(b < kMaxVoxBlocks ? (b < 1 ? 1 : b) : kMaxVoxBlocks);
+  const long long b = (n + kVoxThreads - 1) / kVoxThreads;
+  return (int)std::max(1LL, std::min<long long>(b, kMaxVoxBlocks));
+}
+
+void upload_descs(Engine& e) {
+  HIPCALL(hipMemcpyAsync(e.ddesc, e.hdesc, e.P.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, e.stream));
+  sync(e);
+}
+
+bool class_active(Engine& e, const ShapeClass& c) {
+  for (int p : c.probs)
+    if (e.hdesc[p].active) return true;
+  return false;
 }
 
 // ------------------------------------------------------------------ pass launchers ----
 template <typename T, int MODE, typename TIN>
-int launch_zfwd(ghom_ctx* c, const ZfwdArgs<T, TIN>& a, const char* name) {
+int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::string& name) {
   int grid = 0;
-  with_split(c->g.nz, [&](auto s) {
+  with_split(c.nz, [&](auto s) {
     using S = decltype(s);
     using Cfg = ZCfg<T, S::A, S::B>;
-    const long long nlines = (long long)c->g.nx * c->g.ny;
+    const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
-    timed(c, name, [&] {
-      hipLaunchKernelGGL((zfwd_kernel<T, S::A, S::B, MODE, TIN>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g, a);
+    timed(e, name, [&] {
+      hipLaunchKernelGGL((zfwd_batch<T, S::A, S::B, MODE, TIN>), dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT),
+                         0, e.stream, e.ddesc, c.ids, role, update_p);
     });
   });
   return grid;
 }
 
-template <typename T, typename TOUT, bool CGU = false>
-int launch_zinv(ghom_ctx* c, const ZinvArgs<T, TOUT>& a, const char* name) {
+template <typename T, typename TOUT, bool CGU>
+int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name) {
   int grid = 0;
-  with_split(c->g.nz, [&](auto s) {
+  with_split(c.nz, [&](auto s) {
     using S = decltype(s);
     using Cfg = ZCfg<T, S::A, S::B>;
-    const long long nlines = (long long)c->g.nx * c->g.ny;
+    const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
-    timed(c, name, [&] {
-      hipLaunchKernelGGL((zinv_kernel<T, S::A, S::B, TOUT, CGU>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g, a);
+    timed(e, name, [&] {
+      hipLaunchKernelGGL((zinv_batch<T, S::A, S::B, TOUT, CGU>), dim3(grid, 1, (unsigned)c.probs.size()),
+                         dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role);
     });
   });
   return grid;
 }
 
 template <typename T, int DIR>
-void launch_ypass(ghom_ctx* c, Slab sl, const CGScalars* sc, const char* name) {
-  with_split(c->g.ny, [&](auto s) {
+void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string& name) {
+  with_split(c.ny, [&](auto s) {
     using S = decltype(s);
     using Cfg = ColCfg<T, S::A, S::B>;
-    const long long ncols = 9LL * c->g.nx * sl.nkz;
+    const long long ncols = 9LL * c.nx * sl.nkz;
     const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-    timed(c, name, [&] {
-      hipLaunchKernelGGL((ypass_kernel<T, S::A, S::B, DIR>), dim3(grid), dim3(Cfg::NT), 0, c->stream, c->g, sl,
-                         reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 1), sc);
+    timed(e, name, [&] {
+      hipLaunchKernelGGL((ypass_batch<T, S::A, S::B, DIR>), dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0,
+                         e.stream, e.ddesc, c.ids, role, sl);
     });
   });
 }
 
-enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2 };
-
-template <typename T> int& xproj_choice(ghom_ctx* c) { return c->xproj_var[sizeof(T) == 8 ? 0 : 1]; }
-
 template <typename T>
-void launch_xproj_variant(ghom_ctx* c, int variant, Slab sl, const ProjParams& pp, const CGScalars* sc) {
-  with_split(c->g.nx, [&](auto s) {
+void launch_xproj_variant(Engine& e, ShapeClass& c, int variant, int role, Slab sl) {
+  with_split(c.nx, [&](auto s) {
     using S = decltype(s);
-    const long long ncols = (long long)c->g.ny * sl.nkz;
+    const long long ncols = (long long)c.ny * sl.nkz;
     if (variant == XPROJ_ROWS) {
       using Cfg = ColCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      hipLaunchKernelGGL((xproj_rows_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g, sl,
-                         reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 0), pp, sc);
+      hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B>), dim3(grid, 3, (unsigned)c.probs.size()), dim3(Cfg::NT), 0,
+                         e.stream, e.ddesc, c.ids, role, sl);
     } else {
       using Cfg = XCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      hipLaunchKernelGGL((xproj_groups_kernel<T, S::A, S::B>), dim3(grid, 3), dim3(Cfg::NT), 0, c->stream, c->g, sl,
-                         reinterpret_cast<cx<T>*>(c->H), twid<T>(c, 0), pp, sc);
+      hipLaunchKernelGGL((xproj_groups_batch<T, S::A, S::B>), dim3(grid, 3, (unsigned)c.probs.size()), dim3(Cfg::NT),
+                         0, e.stream, e.ddesc, c.ids, role, sl);
     }
   });
 }
 
-template <typename T>
-void launch_xproj(ghom_ctx* c, Slab sl, const ProjParams& pp, const CGScalars* sc, const char* name) {
-  const int v = xproj_choice<T>(c);
-  timed(c, name, [&] { launch_xproj_variant<T>(c, v == XPROJ_TUNED ? XPROJ_ROWS : v, sl, pp, sc); });
-}
+template <typename T> int& xproj_choice(ShapeClass& c) { return c.xproj_var[sizeof(T) == 8 ? 0 : 1]; }
 
-// The three middle passes (y forward, x with the projection, y inverse), kz-slab by slab.
+// y forward, x with the projection, y inverse; kz-slab by slab
 template <typename T>
-void middle_passes(ghom_ctx* c, const ProjParams& pp, const CGScalars* sc, const std::string& pre) {
+void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre) {
   const std::string t = tname<T>();
   const std::string n2 = pre + "yfwd_" + t, n3 = pre + "xproj_" + t, n4 = pre + "yinv_" + t;
-  const int ns = std::max(1, std::min(c->zslabs, c->g.nzh));
-  const int per = (c->g.nzh + ns - 1) / ns;
-  for (int kz0 = 0; kz0 < c->g.nzh; kz0 += per) {
-    const Slab sl{kz0, std::min(per, c->g.nzh - kz0)};
-    launch_ypass<T, -1>(c, sl, sc, n2.c_str());
-    launch_xproj<T>(c, sl, pp, sc, n3.c_str());
-    launch_ypass<T, +1>(c, sl, sc, n4.c_str());
+  const int nzh = c.g.nzh;
+  const int ns = std::max(1, std::min(e.zslabs, nzh));
+  const int per = (nzh + ns - 1) / ns;
+  const int v = xproj_choice<T>(c) == XPROJ_TUNED ? XPROJ_ROWS : xproj_choice<T>(c);
+  for (int kz0 = 0; kz0 < nzh; kz0 += per) {
+    const Slab sl{kz0, std::min(per, nzh - kz0)};
+    launch_ypass<T, -1>(e, c, role, sl, n2);
+    timed(e, n3, [&] { launch_xproj_variant<T>(e, c, v, role, sl); });
+    launch_ypass<T, +1>(e, c, role, sl, n4);
   }
 }
 
-// Autotuner: times both x-pass variants on the (scratch) spectrum buffer with HIP events
-// and keeps the faster one for this precision and grid.  Runs at context creation, when the
-// spectrum holds no data; the result is reported by ghom_get_option.
+// Autotuner: times both x-pass variants on the class's (zeroed, unused) spectra with HIP
+// events and keeps the faster one for this precision and shape.
 template <typename T>
-void tune_xproj(ghom_ctx* c) {
-  ProjParams pp{};
-  pp.post = 1.0 / (double)c->g.N;
-  hipEvent_t e0 = get_event(c), e1 = get_event(c);
+void tune_xproj(Engine& e, ShapeClass& c) {
+  hipEvent_t e0 = get_event(e), e1 = get_event(e);
   float best = 0.f;
   int best_v = XPROJ_ROWS;
+  const Slab full{0, c.g.nzh};
   for (int v : {XPROJ_ROWS, XPROJ_GROUPS}) {
-    const Slab full{0, c->g.nzh};
-    launch_xproj_variant<T>(c, v, full, pp, nullptr);  // warm-up
+    launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full);  // warm-up
     HIPCALL(hipGetLastError());
     float tmin = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
-      HIPCALL(hipEventRecord(e0, c->stream));
-      launch_xproj_variant<T>(c, v, full, pp, nullptr);
+      HIPCALL(hipEventRecord(e0, e.stream));
+      launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full);
       HIPCALL(hipGetLastError());
-      HIPCALL(hipEventRecord(e1, c->stream));
+      HIPCALL(hipEventRecord(e1, e.stream));
       HIPCALL(hipEventSynchronize(e1));
       float ms = 0.f;
       HIPCALL(hipEventElapsedTime(&ms, e0, e1));
@@ -305,331 +311,687 @@ void tune_xproj(ghom_ctx* c) {
       best_v = v;
     }
   }
-  c->ev_pool.push_back(e0);
-  c->ev_pool.push_back(e1);
+  e.ev_pool.push_back(e0);
+  e.ev_pool.push_back(e1);
   xproj_choice<T>(c) = best_v;
 }
-
-ProjParams make_proj(ghom_ctx* c, double scale, const double* Pbar) {
-  ProjParams pp{};
-  pp.mask = 0;
-  for (int i = 0; i < 9; ++i)
-    if (c->mask[i]) pp.mask |= 1u << i;
-  pp.post = scale / (double)c->g.N;
-  for (int i = 0; i < 9; ++i) pp.off[i] = Pbar ? (double)c->g.N * Pbar[i] : 0.0;
-  return pp;
-}
-
-// out = scale * G*(in - Pbar) on FP64 output; `in` of type TIN; optional self dot
-template <typename TIN>
-int project64(ghom_ctx* c, const TIN* in, double* out, double scale, const double* Pbar, bool self_dot,
-              const char* tag) {
-  ZfwdArgs<double, TIN> za{};
-  za.in = in;
-  za.H = reinterpret_cast<cx<double>*>(c->H);
-  za.tw = c->tw64[2];
-  std::string n1 = std::string(tag) + "_zfwd_f64", n2 = std::string(tag) + "_yfwd_f64",
-              n3 = std::string(tag) + "_xproj_f64", n4 = std::string(tag) + "_yinv_f64",
-              n5 = std::string(tag) + "_zinv_f64";
-  launch_zfwd<double, Z_PLAIN, TIN>(c, za, n1.c_str());
-  middle_passes<double>(c, make_proj(c, scale, Pbar), nullptr, std::string(tag) + "_");
-  ZinvArgs<double, double> zi{};
-  zi.H = reinterpret_cast<cx<double>*>(c->H);
-  zi.out = out;
-  zi.dot_with = self_dot ? out : nullptr;
-  zi.partials = c->partials;
-  zi.tw = c->tw64[2];
-  return launch_zinv<double, double>(c, zi, n5.c_str());
-}
-
-// The operator A(v) = G*(K : v) in the CG type.
-//  plain (cg == false): Av written to `Av`.
-//  CG step (cg == true): v is the direction p (first updated to r + beta p when update_p);
-//    zfwd leaves per-block partials of p : K : p (= p . A p, p lying in the range of G*) for
-//    the alpha kernel, and zinv applies x += alpha p, r -= alpha A p with partials of r.r.
-template <typename T>
-void operator_apply(ghom_ctx* c, T* v, T* Av, bool cg, bool update_p, const CGScalars* sc, int* grid_out) {
-  ZfwdArgs<T, T> za{};
-  za.p = v;
-  za.r = reinterpret_cast<const T*>(c->r);
-  za.update_p = update_p ? 1 : 0;
-  za.state = reinterpret_cast<const T*>(c->state);
-  za.phase = c->phase;
-  za.C6 = mat_table<T>(c);
-  za.has_scale = c->scale != nullptr;
-  za.partials = cg ? c->partials : nullptr;
-  za.H = reinterpret_cast<cx<T>*>(c->H);
-  za.tw = twid<T>(c, 2);
-  za.sc = sc;
-  const std::string t = tname<T>();
-  const std::string n1 = "op_zfwd_" + t, n2 = "op_yfwd_" + t, n3 = "op_xproj_" + t, n4 = "op_yinv_" + t,
-                    n5 = "op_zinv_" + t;
-  int gz;
-  if (c->kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(c, za, n1.c_str());
-  else gz = launch_zfwd<T, Z_SVK, T>(c, za, n1.c_str());
-  if (grid_out) *grid_out = gz;
-  if (cg) {
-    timed(c, "cg_scalar", [&] {
-      hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gz, 1);
-    });
-  }
-  middle_passes<T>(c, make_proj(c, 1.0, nullptr), sc, "op_");
-  ZinvArgs<T, T> zi{};
-  zi.H = reinterpret_cast<cx<T>*>(c->H);
-  zi.partials = c->partials;
-  zi.tw = twid<T>(c, 2);
-  zi.sc = sc;
-  if (cg) {
-    zi.x = reinterpret_cast<T*>(c->x);
-    zi.r = reinterpret_cast<T*>(c->r);
-    zi.p = v;
-    launch_zinv<T, T, true>(c, zi, n5.c_str());
-  } else {
-    zi.out = Av;
-    launch_zinv<T, T, false>(c, zi, n5.c_str());
-  }
-}
-
-void sync(ghom_ctx* c) { HIPCALL(hipStreamSynchronize(c->stream)); }
-
-__global__ void zero_int_kernel(int* f) { *f = 0; }
 
 __global__ void fill_zero_kernel(long long n, double* p) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0.0;
 }
 
-// ------------------------------------------------------------------ method steps -------
-// constitutive update: P, tangent state, <F>, <P>; EDOMAIN if det F <= 0 anywhere
-void constitutive(ghom_ctx* c) {
-  const int grid = vox_blocks(c->g.N);
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, c->flag);
-  HIPCALL(hipGetLastError());
-  timed(c, "constitutive", [&] {
-    if (c->kind == MAT_NH) {
-      if (c->prec == GHOM_FP64)
-        hipLaunchKernelGGL((constitutive_kernel<double, MAT_NH>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g,
-                           c->F, c->P, (double*)c->state, c->phase, c->scale, c->mat, c->partials, c->flag);
-      else
-        hipLaunchKernelGGL((constitutive_kernel<float, MAT_NH>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g,
-                           c->F, c->P, (float*)c->state, c->phase, c->scale, c->mat, c->partials, c->flag);
-    } else {
-      if (c->prec == GHOM_FP64)
-        hipLaunchKernelGGL((constitutive_kernel<double, MAT_SVK>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g,
-                           c->F, c->P, (double*)c->state, c->phase, c->scale, c->mat, c->partials, c->flag);
-      else
-        hipLaunchKernelGGL((constitutive_kernel<float, MAT_SVK>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g,
-                           c->F, c->P, (float*)c->state, c->phase, c->scale, c->mat, c->partials, c->flag);
-    }
-  });
-  timed(c, "reduce", [&] {
-    hipLaunchKernelGGL(sum_columns_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, grid, 18, 0,
-                       c->red);
-  });
-  HIPCALL(hipMemcpyAsync(c->host_red, c->red, 18 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCALL(hipMemcpyAsync(c->host_red + 24, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  sync(c);
-  int bad = 0;
-  std::memcpy(&bad, c->host_red + 24, sizeof(int));
-  for (int i = 0; i < 9; ++i) {
-    c->Favg[i] = c->host_red[i] / (double)c->g.N;
-    c->Pavg[i] = c->host_red[9 + i] / (double)c->g.N;
+// which: -1 both precisions, 0 float64 only, 1 float32 only
+void tune_class(Engine& e, ShapeClass& c, int which) {
+  for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
+  for (int p : c.probs) {
+    e.hdesc[p].active = 1;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, 18 * c.g.Nh,
+                       reinterpret_cast<double*>(e.hdesc[p].H));
+    HIPCALL(hipGetLastError());
   }
-  c->state_valid = true;
-  if (bad) {
-    c->state_valid = false;
-    fail(GHOM_EDOMAIN, "det F <= 0 at some voxel");
-  }
+  upload_descs(e);
+  if (which != 1) tune_xproj<double>(e, c);
+  if (e.prec == GHOM_FP32_SPLIT && which != 0) tune_xproj<float>(e, c);
+  sync(e);
 }
 
-// b = -G*(P - Pbar) in FP64; returns rms(b)
-double residual(ghom_ctx* c, const double* Pbar) {
-  const int grid = project64<double>(c, c->P, c->b, -1.0, Pbar, true, "res");
-  timed(c, "reduce", [&] {
-    hipLaunchKernelGGL(sum_columns_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, grid, 1, 0, c->red);
-  });
-  HIPCALL(hipMemcpyAsync(c->host_red, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  sync(c);
-  return std::sqrt(c->host_red[0] / (double)c->g.N);
+// out = scale * G*(in - Pbar) in float64 for every active problem of a class
+// role: ROLE_RESID (P -> b, with b.b partials), ROLE_REPROJ (x -> dF64), ROLE_PROJ (in -> out)
+int project64(Engine& e, ShapeClass& c, int role, const std::string& tag) {
+  const std::string pre = tag + "_";
+  if (role == ROLE_REPROJ) launch_zfwd<double, Z_PLAIN, float>(e, c, role, 0, pre + "zfwd_f64");
+  else launch_zfwd<double, Z_PLAIN, double>(e, c, role, 0, pre + "zfwd_f64");
+  middle_passes<double>(e, c, role, pre);
+  return launch_zinv<double, double, false>(e, c, role, pre + "zinv_f64");
 }
 
-__global__ void cg_setup_kernel(CGScalars* sc, double thresh, int max_it) {
-  sc->thresh = thresh;
-  sc->max_it = max_it;
-  sc->it = 0;
-  sc->done = 0;
-  sc->status = 0;
-}
-
-struct CGResult {
-  int iters;
-  int status;
-};
-
-// conjugate gradients on A dF = b from dF = 0 (x holds the result); stop rule of Sec. 4
+// A(v) = G*(K : v) in the CG type.  ROLE_OP_CG: one CG step (see the kernels); returns the
+// z-pass grid (the partial count of its reductions).  ROLE_OP_PLAIN: in -> out.
 template <typename T>
-CGResult cg_solve(ghom_ctx* c, double rms_b, double* t_ms) {
+int operator_apply(Engine& e, ShapeClass& c, int role, bool update_p) {
+  const std::string t = tname<T>();
+  int gz;
+  if (c.kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p ? 1 : 0, "op_zfwd_" + t);
+  else gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p ? 1 : 0, "op_zfwd_" + t);
+  if (role == ROLE_OP_CG) {
+    timed(e, "cg_scalar", [&] {
+      hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
+                         c.ids, gz, 1);
+    });
+  }
+  middle_passes<T>(e, c, role, "op_");
+  if (role == ROLE_OP_CG) launch_zinv<T, T, true>(e, c, role, "op_zinv_" + t);
+  else launch_zinv<T, T, false>(e, c, role, "op_zinv_" + t);
+  return gz;
+}
+
+// ------------------------------------------------------------------ method steps -------
+// Constitutive update of every active problem: P, tangent state, <F>, <P>.  Problems with
+// det F <= 0 get EDOMAIN and stop.
+void constitutive(Engine& e) {
+  for (auto& c : e.C) {
+    if (!class_active(e, c)) continue;
+    const int np = (int)c.probs.size();
+    hipLaunchKernelGGL(zero_flag_batch, dim3((np + 255) / 256), dim3(256), 0, e.stream, e.ddesc, c.ids, np);
+    HIPCALL(hipGetLastError());
+    timed(e, "constitutive", [&] {
+      const dim3 grid(c.vb, 1, np);
+      if (c.kind == MAT_NH) {
+        if (e.prec == GHOM_FP64)
+          hipLaunchKernelGGL((constitutive_batch<double, MAT_NH>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+        else
+          hipLaunchKernelGGL((constitutive_batch<float, MAT_NH>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+      } else {
+        if (e.prec == GHOM_FP64)
+          hipLaunchKernelGGL((constitutive_batch<double, MAT_SVK>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+        else
+          hipLaunchKernelGGL((constitutive_batch<float, MAT_SVK>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+      }
+    });
+    timed(e, "reduce", [&] {
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 18, 0);
+    });
+  }
+  const size_t n = e.P.size();
+  HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  HIPCALL(hipMemcpyAsync(e.host_flags, e.flags, n * sizeof(int), hipMemcpyDeviceToHost, e.stream));
+  sync(e);
+  for (size_t p = 0; p < n; ++p) {
+    if (!e.hdesc[p].active) continue;
+    Prob& q = e.P[p];
+    const double N = (double)e.C[q.cls].g.N;
+    for (int i = 0; i < 9; ++i) {
+      q.Favg[i] = e.host_red[32 * p + i] / N;
+      q.Pavg[i] = e.host_red[32 * p + 9 + i] / N;
+    }
+    q.state_valid = true;
+    if (e.host_flags[p]) {
+      q.state_valid = false;
+      q.status = GHOM_EDOMAIN;
+      q.msg = "det F <= 0 at some voxel";
+      q.running = false;
+    }
+  }
+}
+
+// b = -G*(P - Pbar) in FP64 for every active problem; sets rms_b
+void residual(Engine& e) {
+  for (auto& c : e.C) {
+    if (!class_active(e, c)) continue;
+    const int grid = project64(e, c, ROLE_RESID, "res");
+    timed(e, "reduce", [&] {
+      hipLaunchKernelGGL(sum_columns_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
+                         c.ids, grid, 1, 0);
+    });
+  }
+  const size_t n = e.P.size();
+  HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  sync(e);
+  for (size_t p = 0; p < n; ++p)
+    if (e.hdesc[p].active) e.P[p].rms_b = std::sqrt(e.host_red[32 * p] / (double)e.C[e.P[p].cls].g.N);
+}
+
+// Conjugate gradients on A dF = b from dF = 0 for every active problem; the stop test of
+// each problem is set in its descriptor (cg_thresh, max_cg).  Returns when all are done.
+template <typename T>
+void cg_solve(Engine& e, double* t_ms) {
   const auto t0 = std::chrono::steady_clock::now();
-  const double tol = std::max(c->cg_tol, c->cg_forcing * rms_b);
-  const long long n9 = 9 * c->g.N;
-  T* x = reinterpret_cast<T*>(c->x);
-  T* r = reinterpret_cast<T*>(c->r);
-  T* p = reinterpret_cast<T*>(c->p);
-  hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(1), 0, c->stream, c->sc, tol * tol * (double)c->g.N, c->max_cg);
-  HIPCALL(hipGetLastError());
-  const int gi = vox_blocks(n9);
-  timed(c, "cg_init", [&] {
-    hipLaunchKernelGGL((cg_init_kernel<T>), dim3(gi), dim3(kVoxThreads), 0, c->stream, n9, c->b, x, r, p, c->partials);
-  });
-  timed(c, "cg_scalar", [&] {
-    hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gi, 0);
-  });
+  long long vox = 0;
+  for (auto& c : e.C) {
+    const int np = (int)c.probs.size();
+    for (int p : c.probs)
+      if (e.hdesc[p].active) vox += c.g.N;
+    const int gi = vox_blocks(9 * c.g.N);
+    timed(e, "cg_init", [&] {
+      hipLaunchKernelGGL((cg_init_batch<T>), dim3(gi, 1, np), dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+    });
+    if (!class_active(e, c)) continue;
+    timed(e, "cg_scalar", [&] {
+      hipLaunchKernelGGL(cg_scalar_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 0);
+    });
+  }
   int enqueued = 0;
-  int chunk = c->g.N >= (1LL << 21) ? 1 : (c->g.N >= (1LL << 18) ? 2 : 8);
+  int chunk = vox >= (1LL << 21) ? 1 : (vox >= (1LL << 18) ? 2 : 8);
+  const size_t n = e.P.size();
   for (;;) {
     for (int i = 0; i < chunk; ++i, ++enqueued) {
-      int gz = 0;
-      operator_apply<T>(c, p, nullptr, true, enqueued > 0, c->sc, &gz);
-      timed(c, "cg_scalar", [&] {
-        hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->sc, c->partials, gz, 2);
-      });
+      for (auto& c : e.C) {
+        if (!class_active(e, c)) continue;
+        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, enqueued > 0);
+        timed(e, "cg_scalar", [&] {
+          hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
+                             c.ids, gz, 2);
+        });
+      }
     }
-    HIPCALL(hipMemcpyAsync(c->host_sc, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
-    sync(c);
-    if (c->host_sc->done) break;
-    if (chunk < 8 && c->g.N < (1LL << 21)) chunk *= 2;
+    HIPCALL(hipMemcpyAsync(e.host_sc, e.sc, n * sizeof(CGScalars), hipMemcpyDeviceToHost, e.stream));
+    sync(e);
+    bool all = true;
+    for (size_t p = 0; p < n; ++p)
+      if (e.hdesc[p].active && !e.host_sc[p].done) all = false;
+    if (all) break;
+    if (chunk < 8 && vox < (1LL << 21)) chunk *= 2;
   }
   if (t_ms) *t_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return CGResult{c->host_sc->it, c->host_sc->status};
 }
 
-// F += dF (dF in FP64 or the CG type); returns crit = max |dF| / |<F>|
-template <typename TD>
-double newton_update(ghom_ctx* c, const TD* dF) {
-  const int grid = vox_blocks(c->g.N);
-  timed(c, "newton_update", [&] {
-    hipLaunchKernelGGL((newton_update_kernel<TD>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g, c->F, dF,
-                       c->partials);
-  });
-  timed(c, "reduce", [&] {
-    hipLaunchKernelGGL(sum_columns_kernel, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, grid, 10, 1, c->red);
-  });
-  HIPCALL(hipMemcpyAsync(c->host_red, c->red, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  sync(c);
-  double nf = 0.0;
-  for (int i = 0; i < 9; ++i) {
-    const double m = c->host_red[1 + i] / (double)c->g.N;
-    nf += m * m;
+// F += dF for every active problem; sets crit = max |dF| / |<F>|
+void newton_update(Engine& e, std::vector<double>& crit) {
+  for (auto& c : e.C) {
+    if (!class_active(e, c)) continue;
+    const int np = (int)c.probs.size();
+    timed(e, "newton_update", [&] {
+      hipLaunchKernelGGL(newton_update_batch, dim3(c.vb, 1, np), dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+    });
+    timed(e, "reduce", [&] {
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 10, 1);
+    });
   }
-  c->state_valid = false;
-  return std::sqrt(c->host_red[0]) / std::sqrt(nf);
+  const size_t n = e.P.size();
+  HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  sync(e);
+  crit.assign(n, 0.0);
+  for (size_t p = 0; p < n; ++p) {
+    if (!e.hdesc[p].active) continue;
+    const double N = (double)e.C[e.P[p].cls].g.N;
+    double nf = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      const double m = e.host_red[32 * p + 1 + i] / N;
+      nf += m * m;
+    }
+    crit[p] = std::sqrt(e.host_red[32 * p]) / std::sqrt(nf);
+    e.P[p].state_valid = false;
+  }
 }
 
-// One Newton solve (eq. 20) at the current increment with stress target Pbar.
-int newton(ghom_ctx* c, const double* Pbar, ghom_step_info* info) {
+void set_active_from_running(Engine& e, const std::vector<int>& set) {
+  for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
+  for (int p : set) e.hdesc[p].active = e.P[p].running ? 1 : 0;
+  upload_descs(e);
+}
+
+bool any_running(Engine& e, const std::vector<int>& set) {
+  for (int p : set)
+    if (e.P[p].running) return true;
+  return false;
+}
+
+// Newton (eq. 20) for the problems in `set`, each at its own stress target (descriptor
+// pbar).  Per-problem outcome in P[p].status / info.
+void newton(Engine& e, const std::vector<int>& set) {
   const auto t0 = std::chrono::steady_clock::now();
-  ghom_step_info loc{};
-  loc.crit = INFINITY;
-  int rc = GHOM_ENOTCONVERGED;
-  try {
-    for (int it = 0; it < c->max_newton; ++it) {
-      loc.newton_iters += 1;
-      constitutive(c);
-      const double rms_b = residual(c, Pbar);
-      loc.res_rms = rms_b;
-      if (!std::isfinite(rms_b)) fail(GHOM_EDOMAIN, "non-finite Newton residual");
-      if (rms_b <= c->cg_tol) {
-        rc = GHOM_OK;
-        break;
-      }
-      CGResult cr = c->prec == GHOM_FP64 ? cg_solve<double>(c, rms_b, &loc.t_cg_ms)
-                                         : cg_solve<float>(c, rms_b, &loc.t_cg_ms);
-      loc.cg_iters_total += cr.iters;
-      if (cr.status == 2) {
-        if (cr.iters == 0) fail(GHOM_ESINGULAR, "CG breakdown (p.Ap <= 0) at its first iteration");
-        loc.cg_breakdowns += 1;
-      } else if (cr.status == 3) {
-        fail(GHOM_ENOTCONVERGED, "CG reached max_cg");
-      }
-      double crit;
-      if (c->prec == GHOM_FP64) {
-        crit = newton_update<double>(c, reinterpret_cast<const double*>(c->x));
+  for (int p : set) {
+    Prob& q = e.P[p];
+    q.running = true;
+    q.status = GHOM_ENOTCONVERGED;
+    q.msg = "Newton reached max_newton";
+    q.info = ghom_step_info{};
+    q.info.crit = INFINITY;
+  }
+  std::vector<double> crit;
+  for (int it = 0; it < e.max_newton && any_running(e, set); ++it) {
+    set_active_from_running(e, set);
+    for (int p : set)
+      if (e.P[p].running) e.P[p].info.newton_iters += 1;
+    constitutive(e);
+    set_active_from_running(e, set);
+    if (!any_running(e, set)) break;
+    residual(e);
+    for (int p : set) {
+      Prob& q = e.P[p];
+      if (!q.running) continue;
+      q.info.res_rms = q.rms_b;
+      if (!std::isfinite(q.rms_b)) {
+        q.status = GHOM_EDOMAIN;
+        q.msg = "non-finite Newton residual";
+        q.running = false;
+      } else if (q.rms_b <= e.cg_tol) {
+        q.status = GHOM_OK;
+        q.running = false;
       } else {
-        project64<float>(c, reinterpret_cast<const float*>(c->x), c->dF64, 1.0, nullptr, false, "reproj");
-        crit = newton_update<double>(c, c->dF64);
-      }
-      loc.crit = crit;
-      if (!std::isfinite(crit)) fail(GHOM_EDOMAIN, "non-finite Newton correction");
-      if (crit < c->newton_tol) {
-        rc = GHOM_OK;
-        break;
+        const double tol = std::max(e.cg_tol, e.cg_forcing * q.rms_b);
+        e.hdesc[p].cg_thresh = tol * tol * (double)e.C[q.cls].g.N;
+        e.hdesc[p].max_cg = e.max_cg;
       }
     }
-    constitutive(c);  // P and the averages of the final F
-  } catch (const ApiError& e) {
-    loc.status = e.code;
-    loc.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (info) *info = loc;
-    throw;
+    set_active_from_running(e, set);
+    if (!any_running(e, set)) break;
+    double tcg = 0.0;
+    if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg);
+    else cg_solve<float>(e, &tcg);
+    for (int p : set) {
+      Prob& q = e.P[p];
+      if (!q.running) continue;
+      q.info.t_cg_ms += tcg;
+      const CGScalars& s = e.host_sc[p];
+      q.info.cg_iters_total += s.it;
+      if (s.status == 2) {
+        if (s.it == 0) {
+          q.status = GHOM_ESINGULAR;
+          q.msg = "CG breakdown (p.Ap <= 0) at its first iteration";
+          q.running = false;
+        } else {
+          q.info.cg_breakdowns += 1;
+        }
+      } else if (s.status == 3) {
+        q.status = GHOM_ENOTCONVERGED;
+        q.msg = "CG reached max_cg";
+        q.running = false;
+      }
+    }
+    set_active_from_running(e, set);
+    if (!any_running(e, set)) break;
+    if (e.prec == GHOM_FP32_SPLIT)
+      for (auto& c : e.C)
+        if (class_active(e, c)) project64(e, c, ROLE_REPROJ, "reproj");
+    newton_update(e, crit);
+    for (int p : set) {
+      Prob& q = e.P[p];
+      if (!q.running) continue;
+      q.info.crit = crit[p];
+      if (!std::isfinite(crit[p])) {
+        q.status = GHOM_EDOMAIN;
+        q.msg = "non-finite Newton correction";
+        q.running = false;
+      } else if (crit[p] < e.newton_tol) {
+        q.status = GHOM_OK;
+        q.running = false;
+      }
+    }
   }
-  if (rc != GHOM_OK) c->err = "Newton reached max_newton";
-  loc.status = rc;
-  loc.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (info) *info = loc;
-  return rc;
-}
-
-void target_split(ghom_ctx* c, int k, double* Pbar) {
-  for (int i = 0; i < 9; ++i) Pbar[i] = (k >= 1 && c->mask[i]) ? c->target[(size_t)(k - 1) * 9 + i] : 0.0;
-}
-
-void reset_state(ghom_ctx* c) {
-  Shift9 id{};
-  for (int i = 0; i < 9; ++i) id.d[i] = (i % 4 == 0) ? 1.0 : 0.0;
-  hipLaunchKernelGGL(fill9_kernel, dim3(vox_blocks(c->g.N)), dim3(kVoxThreads), 0, c->stream, c->g.N, c->F, id);
-  HIPCALL(hipGetLastError());
-  c->k = 0;
-  c->state_valid = false;
-  for (int i = 0; i < 9; ++i) {
-    c->Favg[i] = id.d[i];
-    c->Pavg[i] = 0.0;
+  for (int p : set) e.P[p].running = false;
+  // P and the averages at the final F of every problem of the solve (not after EDOMAIN)
+  for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
+  for (int p : set) e.hdesc[p].active = e.P[p].status == GHOM_EDOMAIN ? 0 : 1;
+  upload_descs(e);
+  std::vector<int> keep_status(e.P.size());
+  std::vector<std::string> keep_msg(e.P.size());
+  for (int p : set) {
+    keep_status[p] = e.P[p].status;
+    keep_msg[p] = e.P[p].msg;
+  }
+  constitutive(e);
+  for (int p : set)
+    if (keep_status[p] != GHOM_EDOMAIN && e.P[p].state_valid) {
+      e.P[p].status = keep_status[p];
+      e.P[p].msg = keep_msg[p];
+    }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int p : set) {
+    e.P[p].info.t_total_ms = ms;
+    e.P[p].info.status = e.P[p].status;
   }
 }
 
-template <typename T>
-void dev_alloc(T** p, size_t count) {
-  void* q = nullptr;
-  HIPCALL(hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1));
-  *p = reinterpret_cast<T*>(q);
+// Shift the deformation-controlled means to increment k+1 and set the stress targets.
+void begin_increment(Engine& e, const std::vector<int>& set) {
+  for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
+  for (int p : set) {
+    Prob& q = e.P[p];
+    const int k1 = q.k + 1;
+    ProbDesc& d = e.hdesc[p];
+    bool any = false;
+    for (int i = 0; i < 9; ++i) {
+      d.shift[i] = 0.0;
+      d.pbar[i] = 0.0;
+      if (q.mask[i]) {
+        d.pbar[i] = q.target[(size_t)(k1 - 1) * 9 + i];
+      } else {
+        const double prev = (k1 == 1) ? ((i % 4 == 0) ? 1.0 : 0.0) : q.target[(size_t)(k1 - 2) * 9 + i];
+        d.shift[i] = q.target[(size_t)(k1 - 1) * 9 + i] - prev;
+        any = any || d.shift[i] != 0.0;
+      }
+    }
+    d.active = any ? 1 : 0;
+    if (any) q.state_valid = false;
+  }
+  upload_descs(e);
+  for (auto& c : e.C) {
+    if (!class_active(e, c)) continue;
+    timed(e, "shift", [&] {
+      hipLaunchKernelGGL(shift_batch, dim3(c.vb, 1, (unsigned)c.probs.size()), dim3(kVoxThreads), 0, e.stream, e.ddesc,
+                         c.ids);
+    });
+  }
 }
 
-void free_all(ghom_ctx* c) {
-  void* ptrs[] = {c->F, c->P, c->b, c->dF64, c->x, c->r, c->p, c->state, c->H, c->phase, c->scale,
-                  c->mat, c->mat32, c->partials, c->sc, c->flag, c->red, c->tw64[0], c->tw64[1], c->tw64[2],
-                  c->tw32[0], c->tw32[1], c->tw32[2]};
+void set_pbar_current(Engine& e, int p) {
+  Prob& q = e.P[p];
+  for (int i = 0; i < 9; ++i)
+    e.hdesc[p].pbar[i] = (q.k >= 1 && q.mask[i]) ? q.target[(size_t)(q.k - 1) * 9 + i] : 0.0;
+}
+
+// F = I for the given problems
+void reset_state(Engine& e, const std::vector<int>& set) {
+  for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
+  for (int p : set) {
+    e.hdesc[p].active = 1;
+    for (int i = 0; i < 9; ++i) e.hdesc[p].fill[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    Prob& q = e.P[p];
+    q.k = 0;
+    q.state_valid = false;
+    for (int i = 0; i < 9; ++i) {
+      q.Favg[i] = e.hdesc[p].fill[i];
+      q.Pavg[i] = 0.0;
+    }
+  }
+  upload_descs(e);
+  for (auto& c : e.C) {
+    if (!class_active(e, c)) continue;
+    hipLaunchKernelGGL(fill9_batch, dim3(c.vb, 1, (unsigned)c.probs.size()), dim3(kVoxThreads), 0, e.stream, e.ddesc,
+                       c.ids, 0);
+    HIPCALL(hipGetLastError());
+  }
+  sync(e);
+}
+
+// ------------------------------------------------------------------ construction -------
+struct ProbSpec {
+  int nx, ny, nz;
+  double L[3];
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void destroy_engine(Engine* e) {
+  if (!e) return;
+  (void)hipSetDevice(e->device);
+  if (e->stream) (void)hipStreamSynchronize(e->stream);
+  for (auto& q : e->P) {
+    if (q.scale) (void)hipFree(q.scale);
+    if (q.mat) (void)hipFree(q.mat);
+    if (q.mat32) (void)hipFree(q.mat32);
+  }
+  for (auto& c : e->C) {
+    if (c.ids) (void)hipFree(c.ids);
+    for (int a = 0; a < 3; ++a) {
+      if (c.tw64[a]) (void)hipFree(c.tw64[a]);
+      if (c.tw32[a]) (void)hipFree(c.tw32[a]);
+    }
+  }
+  void* ptrs[] = {e->arena, e->ddesc, e->sc, e->red, e->flags};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
-  if (c->host_red) (void)hipHostFree(c->host_red);
-  if (c->host_sc) (void)hipHostFree(c->host_sc);
-  for (auto& kv : c->prof_recs)
+  if (e->hdesc) (void)hipHostFree(e->hdesc);
+  if (e->host_sc) (void)hipHostFree(e->host_sc);
+  if (e->host_red) (void)hipHostFree(e->host_red);
+  if (e->host_flags) (void)hipHostFree(e->host_flags);
+  for (auto& kv : e->prof_recs)
     for (auto& pr : kv.second.pending) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
-  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
+  if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+  delete e;
 }
 
-void require_ready(ghom_ctx* c) {
-  if (!c->kind) fail(GHOM_ESTATE, "no material set");
-  if (!c->mask_set) fail(GHOM_ESTATE, "no control mask set");
+// Allocates every problem's buffers (one arena), the descriptors and the shape classes.
+void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vector<int>& kinds) {
+  const size_t n = specs.size();
+  e.P.resize(n);
+  // shape classes keyed by (nx, ny, nz, kind, cell lengths)
+  for (size_t p = 0; p < n; ++p) {
+    const ProbSpec& s = specs[p];
+    int found = -1;
+    for (size_t c = 0; c < e.C.size(); ++c) {
+      const ShapeClass& k = e.C[c];
+      if (k.nx == s.nx && k.ny == s.ny && k.nz == s.nz && k.kind == kinds[p] && k.g.invL[0] == 1.0 / s.L[0] &&
+          k.g.invL[1] == 1.0 / s.L[1] && k.g.invL[2] == 1.0 / s.L[2])
+        found = (int)c;
+    }
+    if (found < 0) {
+      ShapeClass k;
+      k.nx = s.nx;
+      k.ny = s.ny;
+      k.nz = s.nz;
+      k.kind = kinds[p];
+      k.g.nx = s.nx;
+      k.g.ny = s.ny;
+      k.g.nz = s.nz;
+      k.g.nzh = (s.nz % 2 == 0) ? s.nz / 2 : (s.nz + 1) / 2;
+      k.g.N = (long long)s.nx * s.ny * s.nz;
+      k.g.Nh = (long long)s.nx * s.ny * k.g.nzh;
+      for (int a = 0; a < 3; ++a) k.g.invL[a] = 1.0 / s.L[a];
+      k.vb = vox_blocks(k.g.N);
+      e.C.push_back(k);
+      found = (int)e.C.size() - 1;
+    }
+    e.C[found].probs.push_back((int)p);
+    e.P[p].cls = found;
+    e.P[p].kind = kinds[p];
+  }
+  // partials per problem: the largest block count of any reducing launch
+  size_t np = 64;
+  for (auto& c : e.C) {
+    np = std::max(np, (size_t)c.nx * c.ny / 2 + 64);
+    np = std::max(np, (size_t)c.vb * 18);
+    np = std::max(np, (size_t)vox_blocks(9 * c.g.N));
+  }
+  e.np = np;
+  // arena layout
+  auto sizes = [&](const Geo& g) {
+    const size_t N = (size_t)g.N;
+    size_t b = 0;
+    b += 3 * align256(9 * N * 8);                                       // F, P, b
+    if (e.prec == GHOM_FP32_SPLIT) b += align256(9 * N * 8);            // dF64
+    b += 3 * align256(9 * N * e.tsz);                                   // x, r, p
+    b += align256((size_t)kSVKState * N * e.tsz);                       // state
+    b += align256(9 * (size_t)g.Nh * sizeof(cx<double>));               // spectrum
+    b += align256(N * sizeof(uint16_t));                                // phase
+    b += align256(np * sizeof(double));                                 // partials
+    return b;
+  };
+  std::vector<size_t> off(n);
+  size_t total = 0;
+  for (size_t p = 0; p < n; ++p) {
+    off[p] = total;
+    total += sizes(e.C[e.P[p].cls].g);
+  }
+  HIPCALL(hipMalloc((void**)&e.arena, total));
+  HIPCALL(hipMalloc((void**)&e.ddesc, n * sizeof(ProbDesc)));
+  HIPCALL(hipMalloc((void**)&e.sc, n * sizeof(CGScalars)));
+  HIPCALL(hipMalloc((void**)&e.red, n * 32 * sizeof(double)));
+  HIPCALL(hipMalloc((void**)&e.flags, n * sizeof(int)));
+  HIPCALL(hipHostMalloc((void**)&e.hdesc, n * sizeof(ProbDesc), hipHostMallocDefault));
+  HIPCALL(hipHostMalloc((void**)&e.host_sc, n * sizeof(CGScalars), hipHostMallocDefault));
+  HIPCALL(hipHostMalloc((void**)&e.host_red, n * 32 * sizeof(double), hipHostMallocDefault));
+  HIPCALL(hipHostMalloc((void**)&e.host_flags, n * sizeof(int), hipHostMallocDefault));
+  // twiddles W_n^k = exp(-2 pi i k / n) and device id lists per class
+  for (auto& c : e.C) {
+    const int ns[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a) {
+      std::vector<cx<double>> t64(ns[a]);
+      std::vector<cx<float>> t32(ns[a]);
+      for (int k = 0; k < ns[a]; ++k) {
+        const CosSin cs = cossin_2pi(k, ns[a]);
+        t64[k] = cx<double>{(double)cs.c, (double)-cs.s};
+        t32[k] = cx<float>{(float)cs.c, (float)-cs.s};
+      }
+      HIPCALL(hipMalloc((void**)&c.tw64[a], ns[a] * sizeof(cx<double>)));
+      HIPCALL(hipMalloc((void**)&c.tw32[a], ns[a] * sizeof(cx<float>)));
+      HIPCALL(hipMemcpy(c.tw64[a], t64.data(), ns[a] * sizeof(cx<double>), hipMemcpyHostToDevice));
+      HIPCALL(hipMemcpy(c.tw32[a], t32.data(), ns[a] * sizeof(cx<float>), hipMemcpyHostToDevice));
+    }
+    HIPCALL(hipMalloc((void**)&c.ids, c.probs.size() * sizeof(int)));
+    HIPCALL(hipMemcpy(c.ids, c.probs.data(), c.probs.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  // descriptors
+  for (size_t p = 0; p < n; ++p) {
+    const ShapeClass& c = e.C[e.P[p].cls];
+    const size_t N = (size_t)c.g.N;
+    ProbDesc& d = e.hdesc[p];
+    std::memset(&d, 0, sizeof(ProbDesc));
+    d.g = c.g;
+    d.kind = e.P[p].kind;
+    char* q = e.arena + off[p];
+    auto take = [&](size_t bytes) {
+      char* r = q;
+      q += align256(bytes);
+      return (void*)r;
+    };
+    d.F = (double*)take(9 * N * 8);
+    d.P = (double*)take(9 * N * 8);
+    d.b = (double*)take(9 * N * 8);
+    d.dF64 = e.prec == GHOM_FP32_SPLIT ? (double*)take(9 * N * 8) : nullptr;
+    d.x = take(9 * N * e.tsz);
+    d.r = take(9 * N * e.tsz);
+    d.p = take(9 * N * e.tsz);
+    d.state = take((size_t)kSVKState * N * e.tsz);
+    d.H = take(9 * (size_t)c.g.Nh * sizeof(cx<double>));
+    d.phase = (const uint16_t*)take(N * sizeof(uint16_t));
+    d.partials = (double*)take(np * sizeof(double));
+    for (int a = 0; a < 3; ++a) {
+      d.tw64[a] = c.tw64[a];
+      d.tw32[a] = c.tw32[a];
+    }
+    d.sc = e.sc + p;
+    d.red = e.red + 32 * p;
+    d.flag = e.flags + p;
+  }
+  std::vector<int> all(n);
+  for (size_t p = 0; p < n; ++p) all[p] = (int)p;
+  reset_state(e, all);
+  for (auto& c : e.C) tune_class(e, c, -1);
+}
+
+void check_material(const Prob& q) {
+  if (!q.kind) fail(GHOM_ESTATE, "no material set");
+  if (!q.mask_set) fail(GHOM_ESTATE, "no control mask set");
+}
+
+// Voigt table (36 per phase, order 11 22 33 23 13 12) from C_ijkl, with symmetry checks
+std::vector<double> voigt_table(const double* C, int nphase) {
+  static const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
+  std::vector<double> tab(36 * (size_t)nphase);
+  for (int ph = 0; ph < nphase; ++ph) {
+    const double* Cp = C + 81 * (size_t)ph;
+    auto at = [&](int i, int j, int k, int l) { return Cp[((i * 3 + j) * 3 + k) * 3 + l]; };
+    double scale = 0.0;
+    for (int q = 0; q < 81; ++q) scale = std::max(scale, std::fabs(Cp[q]));
+    const double tol = 1e-12 * (scale > 0 ? scale : 1.0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) {
+            const double v = at(i, j, k, l);
+            if (std::fabs(v - at(j, i, k, l)) > tol || std::fabs(v - at(i, j, l, k)) > tol ||
+                std::fabs(v - at(k, l, i, j)) > tol)
+              fail(GHOM_EINVAL, "stiffness lacks minor or major symmetry");
+          }
+    for (int I = 0; I < 6; ++I)
+      for (int J = 0; J < 6; ++J) tab[36 * (size_t)ph + 6 * I + J] = at(vi[I], vj[I], vi[J], vj[J]);
+  }
+  return tab;
+}
+
+// Sets the material of problem p (kind, phase map, tables) and resets it to F = I.
+void set_material(Engine& e, int p, int kind, const uint16_t* phase, int nphase, const std::vector<double>& tab) {
+  Prob& q = e.P[p];
+  ShapeClass& c = e.C[q.cls];
+  const long long N = c.g.N;
+  for (long long v = 0; v < N; ++v)
+    if (phase[v] >= nphase) fail(GHOM_EINVAL, "phase index out of range");
+  if (c.probs.size() > 1 && c.kind != kind) fail(GHOM_EINVAL, "problems of one shape class need one material law");
+  sync(e);
+  if (q.mat) HIPCALL(hipFree(q.mat));
+  if (q.mat32) HIPCALL(hipFree(q.mat32));
+  q.mat = nullptr;
+  q.mat32 = nullptr;
+  HIPCALL(hipMalloc((void**)&q.mat, tab.size() * sizeof(double)));
+  HIPCALL(hipMemcpy(q.mat, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (kind == MAT_SVK) {
+    std::vector<float> t32(tab.begin(), tab.end());
+    HIPCALL(hipMalloc((void**)&q.mat32, t32.size() * sizeof(float)));
+    HIPCALL(hipMemcpy(q.mat32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  HIPCALL(hipMemcpy(const_cast<uint16_t*>(e.hdesc[p].phase), phase, (size_t)N * sizeof(uint16_t),
+                    hipMemcpyHostToDevice));
+  q.kind = kind;
+  q.nphase = nphase;
+  e.hdesc[p].kind = kind;
+  e.hdesc[p].mat = q.mat;
+  e.hdesc[p].mat32 = q.mat32;
+  c.kind = kind;
+  reset_state(e, {p});
+}
+
+void refresh_averages(Engine& e, int p) {
+  if (e.P[p].state_valid || !e.P[p].kind) return;
+  for (size_t i = 0; i < e.P.size(); ++i) e.hdesc[i].active = (int)i == p ? 1 : 0;
+  upload_descs(e);
+  const int keep = e.P[p].status;
+  constitutive(e);
+  if (!e.P[p].state_valid) fail(GHOM_EDOMAIN, "det F <= 0 at some voxel");
+  e.P[p].status = keep;
+}
+
+void copy_field(Engine& e, int p, int which, double* dst, hipMemcpyKind kind) {
+  if (which != GHOM_FIELD_F && which != GHOM_FIELD_P) fail(GHOM_EINVAL, "bad field request");
+  if (which == GHOM_FIELD_P) {
+    check_material(e.P[p]);
+    refresh_averages(e, p);
+  }
+  sync(e);
+  const size_t bytes = 9 * (size_t)e.C[e.P[p].cls].g.N * sizeof(double);
+  HIPCALL(hipMemcpy(dst, which == GHOM_FIELD_F ? e.hdesc[p].F : e.hdesc[p].P, bytes, kind));
+}
+
+int finish_solve(Engine& e, int p, ghom_step_info* info) {
+  Prob& q = e.P[p];
+  if (info) *info = q.info;
+  if (q.status != GHOM_OK) fail(q.status, q.msg);
+  return GHOM_OK;
 }
 
 }  // namespace
 
 // =====================================================================================
-// C ABI
+// Single-problem context = engine with one problem
 // =====================================================================================
+struct ghom_ctx {
+  Engine* e = nullptr;
+};
+
+struct ghom_batch {
+  Engine* e = nullptr;
+};
+
+namespace {
+
+template <typename F>
+int guard(ghom_ctx* c, F&& f) {
+  if (!c || !c->e) return GHOM_EINVAL;
+  return guarded(c->e, std::forward<F>(f));
+}
+
+template <typename F>
+int guard(ghom_batch* b, F&& f) {
+  if (!b || !b->e) return GHOM_EINVAL;
+  return guarded(b->e, std::forward<F>(f));
+}
+
+Engine* new_engine(int precision, int device, void* hip_stream) {
+  Engine* e = new (std::nothrow) Engine();
+  if (!e) return nullptr;
+  e->device = device;
+  e->prec = precision;
+  e->tsz = precision == GHOM_FP64 ? 8 : 4;
+  return e;
+}
+
+void open_stream(Engine& e, void* hip_stream) {
+  if (hip_stream) {
+    e.stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    HIPCALL(hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking));
+    e.own_stream = true;
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 int ghom_create(ghom_ctx** out, int nx, int ny, int nz, double Lx, double Ly, double Lz, int precision, int device,
@@ -639,112 +1001,41 @@ int ghom_create(ghom_ctx** out, int nx, int ny, int nz, double Lx, double Ly, do
   if (!supported_length(nx) || !supported_length(ny) || !supported_length(nz)) return GHOM_EINVAL;
   if (!(Lx > 0 && Ly > 0 && Lz > 0)) return GHOM_EINVAL;
   if (precision != GHOM_FP64 && precision != GHOM_FP32_SPLIT) return GHOM_EINVAL;
-  ghom_ctx* c = new (std::nothrow) ghom_ctx();
-  if (!c) return GHOM_ENOMEM;
-  c->device = device;
-  c->prec = precision;
-  c->tsz = precision == GHOM_FP64 ? 8 : 4;
-  c->g.nx = nx;
-  c->g.ny = ny;
-  c->g.nz = nz;
-  c->g.nzh = (nz % 2 == 0) ? nz / 2 : (nz + 1) / 2;
-  c->g.N = (long long)nx * ny * nz;
-  c->g.Nh = (long long)nx * ny * c->g.nzh;
-  c->g.invL[0] = 1.0 / Lx;
-  c->g.invL[1] = 1.0 / Ly;
-  c->g.invL[2] = 1.0 / Lz;
-  const int rc = guard(c, [&]() -> int {
-    if (hip_stream) {
-      c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    } else {
-      HIPCALL(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-      c->own_stream = true;
-    }
-    const size_t n9 = 9 * (size_t)c->g.N;
-    dev_alloc(&c->F, n9);
-    dev_alloc(&c->P, n9);
-    dev_alloc(&c->b, n9);
-    if (precision == GHOM_FP32_SPLIT) dev_alloc(&c->dF64, n9);
-    HIPCALL(hipMalloc(&c->x, n9 * c->tsz));
-    HIPCALL(hipMalloc(&c->r, n9 * c->tsz));
-    HIPCALL(hipMalloc(&c->p, n9 * c->tsz));
-    HIPCALL(hipMalloc(&c->state, (size_t)kSVKState * c->g.N * c->tsz));
-    HIPCALL(hipMalloc(&c->H, 9 * (size_t)c->g.Nh * sizeof(cx<double>)));
-    dev_alloc(&c->phase, (size_t)c->g.N);
-    // partials: the largest block count of any reducing launch
-    size_t np = (size_t)kMaxVoxBlocks * 18;
-    const long long nlines = (long long)nx * ny;
-    np = std::max(np, (size_t)nlines + 64);
-    c->npartials = np;
-    dev_alloc(&c->partials, np);
-    dev_alloc(&c->sc, 1);
-    dev_alloc(&c->flag, 4);
-    dev_alloc(&c->red, 32);
-    HIPCALL(hipHostMalloc((void**)&c->host_red, 32 * sizeof(double), hipHostMallocDefault));
-    HIPCALL(hipHostMalloc((void**)&c->host_sc, sizeof(CGScalars), hipHostMallocDefault));
-    const int ns[3] = {nx, ny, nz};
-    for (int a = 0; a < 3; ++a) {
-      std::vector<cx<double>> t64(ns[a]);
-      std::vector<cx<float>> t32(ns[a]);
-      for (int k = 0; k < ns[a]; ++k) {
-        const CosSin cs = cossin_2pi(k, ns[a]);
-        t64[k] = cx<double>{(double)cs.c, (double)-cs.s};
-        t32[k] = cx<float>{(float)cs.c, (float)-cs.s};
-      }
-      dev_alloc(&c->tw64[a], ns[a]);
-      dev_alloc(&c->tw32[a], ns[a]);
-      HIPCALL(hipMemcpy(c->tw64[a], t64.data(), ns[a] * sizeof(cx<double>), hipMemcpyHostToDevice));
-      HIPCALL(hipMemcpy(c->tw32[a], t32.data(), ns[a] * sizeof(cx<float>), hipMemcpyHostToDevice));
-    }
-    reset_state(c);
-    // zero spectrum, then pick the x-pass variants by timing them on it
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(vox_blocks(18 * c->g.Nh)), dim3(kVoxThreads), 0, c->stream,
-                       18 * c->g.Nh, reinterpret_cast<double*>(c->H));
-    HIPCALL(hipGetLastError());
-    tune_xproj<double>(c);
-    if (precision == GHOM_FP32_SPLIT) tune_xproj<float>(c);
-    sync(c);
+  Engine* e = new_engine(precision, device, hip_stream);
+  if (!e) return GHOM_ENOMEM;
+  const int rc = guarded(e, [&]() -> int {
+    open_stream(*e, hip_stream);
+    build_engine(*e, {ProbSpec{nx, ny, nz, {Lx, Ly, Lz}}}, {0});
     return GHOM_OK;
   });
-  if (rc != GHOM_OK) {
-    free_all(c);
-    delete c;
-    return rc;
+  ghom_ctx* c = rc == GHOM_OK ? new (std::nothrow) ghom_ctx() : nullptr;
+  if (!c) {
+    destroy_engine(e);
+    return rc != GHOM_OK ? rc : GHOM_ENOMEM;
   }
+  c->e = e;
   *out = c;
   return GHOM_OK;
 }
 
 void ghom_destroy(ghom_ctx* c) {
   if (!c) return;
-  (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  free_all(c);
+  destroy_engine(c->e);
   delete c;
 }
 
-const char* ghom_last_error(const ghom_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* ghom_last_error(const ghom_ctx* c) { return c && c->e ? c->e->err.c_str() : "null context"; }
 
 int ghom_set_material_neohookean(ghom_ctx* c, const uint16_t* phase, int nphase, const double* mu,
                                  const double* lambda) {
   return guard(c, [&]() -> int {
     if (!phase || !mu || !lambda || nphase < 1 || nphase > 65536) fail(GHOM_EINVAL, "bad neo-Hookean arguments");
-    for (long long v = 0; v < c->g.N; ++v)
-      if (phase[v] >= nphase) fail(GHOM_EINVAL, "phase index out of range");
     std::vector<double> tab(2 * (size_t)nphase);
     for (int i = 0; i < nphase; ++i) {
       tab[2 * i] = mu[i];
       tab[2 * i + 1] = lambda[i];
     }
-    if (c->mat) HIPCALL(hipFree(c->mat));
-    c->mat = nullptr;
-    dev_alloc(&c->mat, tab.size());
-    HIPCALL(hipMemcpy(c->mat, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCALL(hipMemcpy(c->phase, phase, (size_t)c->g.N * sizeof(uint16_t), hipMemcpyHostToDevice));
-    c->kind = MAT_NH;
-    c->nphase = nphase;
-    reset_state(c);
-    sync(c);
+    set_material(*c->e, 0, MAT_NH, phase, nphase, tab);
     return GHOM_OK;
   });
 }
@@ -752,59 +1043,30 @@ int ghom_set_material_neohookean(ghom_ctx* c, const uint16_t* phase, int nphase,
 int ghom_set_material_svk(ghom_ctx* c, const uint16_t* phase, int nphase, const double* C) {
   return guard(c, [&]() -> int {
     if (!phase || !C || nphase < 1 || nphase > 65536) fail(GHOM_EINVAL, "bad Saint Venant-Kirchhoff arguments");
-    for (long long v = 0; v < c->g.N; ++v)
-      if (phase[v] >= nphase) fail(GHOM_EINVAL, "phase index out of range");
-    // Voigt order 11 22 33 23 13 12
-    static const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
-    std::vector<double> tab(36 * (size_t)nphase);
-    for (int ph = 0; ph < nphase; ++ph) {
-      const double* Cp = C + 81 * (size_t)ph;
-      auto at = [&](int i, int j, int k, int l) { return Cp[((i * 3 + j) * 3 + k) * 3 + l]; };
-      double scale = 0.0;
-      for (int q = 0; q < 81; ++q) scale = std::max(scale, std::fabs(Cp[q]));
-      const double tol = 1e-12 * (scale > 0 ? scale : 1.0);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          for (int k = 0; k < 3; ++k)
-            for (int l = 0; l < 3; ++l) {
-              const double v = at(i, j, k, l);
-              if (std::fabs(v - at(j, i, k, l)) > tol || std::fabs(v - at(i, j, l, k)) > tol ||
-                  std::fabs(v - at(k, l, i, j)) > tol)
-                fail(GHOM_EINVAL, "stiffness lacks minor or major symmetry");
-            }
-      for (int I = 0; I < 6; ++I)
-        for (int J = 0; J < 6; ++J) tab[36 * (size_t)ph + 6 * I + J] = at(vi[I], vj[I], vi[J], vj[J]);
-    }
-    if (c->mat) HIPCALL(hipFree(c->mat));
-    if (c->mat32) HIPCALL(hipFree(c->mat32));
-    c->mat = nullptr;
-    c->mat32 = nullptr;
-    dev_alloc(&c->mat, tab.size());
-    HIPCALL(hipMemcpy(c->mat, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<float> tab32(tab.begin(), tab.end());
-    dev_alloc(&c->mat32, tab32.size());
-    HIPCALL(hipMemcpy(c->mat32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice));
-    HIPCALL(hipMemcpy(c->phase, phase, (size_t)c->g.N * sizeof(uint16_t), hipMemcpyHostToDevice));
-    c->kind = MAT_SVK;
-    c->nphase = nphase;
-    reset_state(c);
-    sync(c);
+    set_material(*c->e, 0, MAT_SVK, phase, nphase, voigt_table(C, nphase));
     return GHOM_OK;
   });
 }
 
 int ghom_set_stiffness_scale(ghom_ctx* c, const double* s) {
   return guard(c, [&]() -> int {
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    const long long N = e.C[q.cls].g.N;
     if (!s) {
-      if (c->scale) HIPCALL(hipFree(c->scale));
-      c->scale = nullptr;
+      sync(e);
+      if (q.scale) HIPCALL(hipFree(q.scale));
+      q.scale = nullptr;
     } else {
-      for (long long v = 0; v < c->g.N; ++v)
+      for (long long v = 0; v < N; ++v)
         if (!(s[v] > 0.0)) fail(GHOM_EINVAL, "stiffness scale must be > 0");
-      if (!c->scale) dev_alloc(&c->scale, (size_t)c->g.N);
-      HIPCALL(hipMemcpy(c->scale, s, (size_t)c->g.N * sizeof(double), hipMemcpyHostToDevice));
+      if (!q.scale) HIPCALL(hipMalloc((void**)&q.scale, (size_t)N * sizeof(double)));
+      sync(e);
+      HIPCALL(hipMemcpy(q.scale, s, (size_t)N * sizeof(double), hipMemcpyHostToDevice));
     }
-    c->state_valid = false;
+    e.hdesc[0].scale = q.scale;
+    e.hdesc[0].has_scale = q.scale != nullptr;
+    q.state_valid = false;
     return GHOM_OK;
   });
 }
@@ -812,11 +1074,16 @@ int ghom_set_stiffness_scale(ghom_ctx* c, const double* s) {
 int ghom_set_control(ghom_ctx* c, const uint8_t mask[9]) {
   return guard(c, [&]() -> int {
     if (!mask) fail(GHOM_EINVAL, "null mask");
-    for (int i = 0; i < 9; ++i) {
+    Prob& q = c->e->P[0];
+    unsigned bits = 0;
+    for (int i = 0; i < 9; ++i)
       if (mask[i] > 1) fail(GHOM_EINVAL, "mask entries must be 0 or 1");
-      c->mask[i] = mask[i];
+    for (int i = 0; i < 9; ++i) {
+      q.mask[i] = mask[i];
+      if (mask[i]) bits |= 1u << i;
     }
-    c->mask_set = true;
+    c->e->hdesc[0].mask = bits;
+    q.mask_set = true;
     return GHOM_OK;
   });
 }
@@ -824,76 +1091,61 @@ int ghom_set_control(ghom_ctx* c, const uint8_t mask[9]) {
 int ghom_set_history(ghom_ctx* c, int nsteps, const double* target) {
   return guard(c, [&]() -> int {
     if (nsteps < 1 || !target) fail(GHOM_EINVAL, "bad history");
-    c->target.assign(target, target + 9 * (size_t)nsteps);
-    c->nsteps = nsteps;
+    Prob& q = c->e->P[0];
+    q.target.assign(target, target + 9 * (size_t)nsteps);
+    q.nsteps = nsteps;
     return GHOM_OK;
   });
+}
+
+static int set_tolerances(Engine& e, double newton_tol, double cg_tol, double cg_forcing, int max_newton, int max_cg) {
+  if (!(newton_tol > 0) || !(cg_tol > 0) || !(cg_forcing >= 0) || max_newton < 1 || max_cg < 1)
+    fail(GHOM_EINVAL, "bad tolerances");
+  e.newton_tol = newton_tol;
+  e.cg_tol = cg_tol;
+  e.cg_forcing = cg_forcing;
+  e.max_newton = max_newton;
+  e.max_cg = max_cg;
+  return GHOM_OK;
 }
 
 int ghom_set_tolerances(ghom_ctx* c, double newton_tol, double cg_tol, double cg_forcing, int max_newton,
                         int max_cg) {
-  return guard(c, [&]() -> int {
-    if (!(newton_tol > 0) || !(cg_tol > 0) || !(cg_forcing >= 0) || max_newton < 1 || max_cg < 1)
-      fail(GHOM_EINVAL, "bad tolerances");
-    c->newton_tol = newton_tol;
-    c->cg_tol = cg_tol;
-    c->cg_forcing = cg_forcing;
-    c->max_newton = max_newton;
-    c->max_cg = max_cg;
-    return GHOM_OK;
-  });
+  return guard(c, [&]() -> int { return set_tolerances(*c->e, newton_tol, cg_tol, cg_forcing, max_newton, max_cg); });
 }
 
 int ghom_step(ghom_ctx* c, ghom_step_info* info) {
   return guard(c, [&]() -> int {
-    require_ready(c);
-    if (c->nsteps == 0) fail(GHOM_ESTATE, "no history set");
-    if (c->k >= c->nsteps) fail(GHOM_ESTATE, "history exhausted");
-    const int k1 = c->k + 1;
-    Shift9 sh{};
-    bool any = false;
-    for (int i = 0; i < 9; ++i) {
-      if (c->mask[i]) continue;
-      const double prev = (k1 == 1) ? ((i % 4 == 0) ? 1.0 : 0.0) : c->target[(size_t)(k1 - 2) * 9 + i];
-      sh.d[i] = c->target[(size_t)(k1 - 1) * 9 + i] - prev;
-      any = any || sh.d[i] != 0.0;
-    }
-    if (any) {
-      timed(c, "shift", [&] {
-        hipLaunchKernelGGL(shift_kernel, dim3(vox_blocks(c->g.N)), dim3(kVoxThreads), 0, c->stream, c->g.N, c->F, sh);
-      });
-      c->state_valid = false;
-    }
-    double Pbar[9];
-    target_split(c, k1, Pbar);
-    int rc;
-    try {
-      rc = newton(c, Pbar, info);
-    } catch (const ApiError& e) {
-      if (e.code == GHOM_ENOTCONVERGED) c->k = k1;
-      throw;
-    }
-    c->k = k1;
-    return rc;
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    check_material(q);
+    if (q.nsteps == 0) fail(GHOM_ESTATE, "no history set");
+    if (q.k >= q.nsteps) fail(GHOM_ESTATE, "history exhausted");
+    begin_increment(e, {0});
+    newton(e, {0});
+    if (q.status == GHOM_OK || q.status == GHOM_ENOTCONVERGED) q.k += 1;
+    return finish_solve(e, 0, info);
   });
 }
 
 int ghom_resolve(ghom_ctx* c, ghom_step_info* info) {
   return guard(c, [&]() -> int {
-    require_ready(c);
-    double Pbar[9];
-    target_split(c, c->k, Pbar);
-    return newton(c, Pbar, info);
+    Engine& e = *c->e;
+    check_material(e.P[0]);
+    set_pbar_current(e, 0);
+    newton(e, {0});
+    return finish_solve(e, 0, info);
   });
 }
 
 int ghom_get_averages(ghom_ctx* c, double Fbar[9], double Pbar[9]) {
   return guard(c, [&]() -> int {
     if (!Fbar || !Pbar) fail(GHOM_EINVAL, "null output");
-    if (!c->state_valid && c->kind) constitutive(c);
+    Engine& e = *c->e;
+    refresh_averages(e, 0);
     for (int i = 0; i < 9; ++i) {
-      Fbar[i] = c->Favg[i];
-      Pbar[i] = c->Pavg[i];
+      Fbar[i] = e.P[0].Favg[i];
+      Pbar[i] = e.P[0].Pavg[i];
     }
     return GHOM_OK;
   });
@@ -901,28 +1153,16 @@ int ghom_get_averages(ghom_ctx* c, double Fbar[9], double Pbar[9]) {
 
 int ghom_get_field(ghom_ctx* c, int which, double* host_out) {
   return guard(c, [&]() -> int {
-    if (!host_out || (which != GHOM_FIELD_F && which != GHOM_FIELD_P)) fail(GHOM_EINVAL, "bad field request");
-    if (which == GHOM_FIELD_P) {
-      require_ready(c);
-      if (!c->state_valid) constitutive(c);
-    }
-    sync(c);
-    HIPCALL(hipMemcpy(host_out, which == GHOM_FIELD_F ? c->F : c->P, 9 * (size_t)c->g.N * sizeof(double),
-                      hipMemcpyDeviceToHost));
+    if (!host_out) fail(GHOM_EINVAL, "null output");
+    copy_field(*c->e, 0, which, host_out, hipMemcpyDeviceToHost);
     return GHOM_OK;
   });
 }
 
 int ghom_get_field_device(ghom_ctx* c, int which, double* dev_out) {
   return guard(c, [&]() -> int {
-    if (!dev_out || (which != GHOM_FIELD_F && which != GHOM_FIELD_P)) fail(GHOM_EINVAL, "bad field request");
-    if (which == GHOM_FIELD_P) {
-      require_ready(c);
-      if (!c->state_valid) constitutive(c);
-    }
-    HIPCALL(hipMemcpyAsync(dev_out, which == GHOM_FIELD_F ? c->F : c->P, 9 * (size_t)c->g.N * sizeof(double),
-                           hipMemcpyDeviceToDevice, c->stream));
-    sync(c);
+    if (!dev_out) fail(GHOM_EINVAL, "null output");
+    copy_field(*c->e, 0, which, dev_out, hipMemcpyDeviceToDevice);
     return GHOM_OK;
   });
 }
@@ -930,65 +1170,75 @@ int ghom_get_field_device(ghom_ctx* c, int which, double* dev_out) {
 int ghom_save_state(ghom_ctx* c, double* F_out, int* step_out) {
   return guard(c, [&]() -> int {
     if (!F_out) fail(GHOM_EINVAL, "null output");
-    sync(c);
-    HIPCALL(hipMemcpy(F_out, c->F, 9 * (size_t)c->g.N * sizeof(double), hipMemcpyDeviceToHost));
-    if (step_out) *step_out = c->k;
+    Engine& e = *c->e;
+    sync(e);
+    HIPCALL(hipMemcpy(F_out, e.hdesc[0].F, 9 * (size_t)e.C[e.P[0].cls].g.N * sizeof(double), hipMemcpyDeviceToHost));
+    if (step_out) *step_out = e.P[0].k;
     return GHOM_OK;
   });
 }
 
 int ghom_load_state(ghom_ctx* c, const double* F_in, int step) {
   return guard(c, [&]() -> int {
-    if (!F_in || step < 0 || (c->nsteps > 0 && step > c->nsteps) || (c->nsteps == 0 && step != 0))
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    if (!F_in || step < 0 || (q.nsteps > 0 && step > q.nsteps) || (q.nsteps == 0 && step != 0))
       fail(GHOM_EINVAL, "bad state");
-    sync(c);
-    HIPCALL(hipMemcpy(c->F, F_in, 9 * (size_t)c->g.N * sizeof(double), hipMemcpyHostToDevice));
-    c->k = step;
-    c->state_valid = false;
+    sync(e);
+    HIPCALL(hipMemcpy(e.hdesc[0].F, F_in, 9 * (size_t)e.C[q.cls].g.N * sizeof(double), hipMemcpyHostToDevice));
+    q.k = step;
+    q.state_valid = false;
     return GHOM_OK;
   });
 }
 
 int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
   return guard(c, [&]() -> int {
-    require_ready(c);
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    check_material(q);
     if (!a || !grad_out) fail(GHOM_EINVAL, "null argument");
-    constitutive(c);
-    // right-hand side G*(a) for a uniform a: only xi = 0 content, kept on stress-controlled
-    // components (the 1/N of G*(a/N) is applied to the solution)
-    Shift9 rhs{};
+    const long long N = e.C[q.cls].g.N;
+    // right-hand side G*(a) of a uniform a: only xi = 0 content, kept on the
+    // stress-controlled components (the 1/N of G*(a/N) is applied to the solution)
     double rr = 0.0;
     for (int i = 0; i < 9; ++i) {
-      rhs.d[i] = c->mask[i] ? a[i] : 0.0;
-      rr += rhs.d[i] * rhs.d[i];
+      e.hdesc[0].fill[i] = q.mask[i] ? a[i] : 0.0;
+      rr += e.hdesc[0].fill[i] * e.hdesc[0].fill[i];
     }
     if (rr == 0.0) {
-      std::vector<double> zero((size_t)c->g.N, 0.0);
-      std::memcpy(grad_out, zero.data(), zero.size() * sizeof(double));
+      std::fill(grad_out, grad_out + N, 0.0);
       return GHOM_OK;
     }
-    hipLaunchKernelGGL(fill9_kernel, dim3(vox_blocks(c->g.N)), dim3(kVoxThreads), 0, c->stream, c->g.N, c->b, rhs);
+    q.state_valid = false;
+    refresh_averages(e, 0);
+    ShapeClass& cl = e.C[q.cls];
+    e.hdesc[0].active = 1;
+    const double tol = std::max(e.cg_tol, e.cg_forcing * std::sqrt(rr));
+    e.hdesc[0].cg_thresh = tol * tol * (double)N;
+    e.hdesc[0].max_cg = e.max_cg;
+    upload_descs(e);
+    hipLaunchKernelGGL(fill9_batch, dim3(cl.vb, 1, 1), dim3(kVoxThreads), 0, e.stream, e.ddesc, cl.ids, 1);
     HIPCALL(hipGetLastError());
-    const double rms_b = std::sqrt(rr);
     double tcg = 0.0;
-    CGResult cr = c->prec == GHOM_FP64 ? cg_solve<double>(c, rms_b, &tcg) : cg_solve<float>(c, rms_b, &tcg);
-    if (cr.status == 2 && cr.iters == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
-    if (cr.status == 3) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+    if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg);
+    else cg_solve<float>(e, &tcg);
+    const CGScalars s = e.host_sc[0];
+    if (s.status == 2 && s.it == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
+    if (s.status == 3) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+    if (e.prec == GHOM_FP32_SPLIT) project64(e, cl, ROLE_REPROJ, "reproj");
     double* grad_dev = nullptr;
-    dev_alloc(&grad_dev, (size_t)c->g.N);
-    const int grid = vox_blocks(c->g.N);
-    if (c->prec == GHOM_FP64) {
-      hipLaunchKernelGGL((adjoint_grad_kernel<double>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g.N,
-                         (const double*)c->x, c->P, c->scale, 1.0 / (double)c->g.N, grad_dev);
-    } else {
-      project64<float>(c, reinterpret_cast<const float*>(c->x), c->dF64, 1.0, nullptr, false, "reproj");
-      hipLaunchKernelGGL((adjoint_grad_kernel<double>), dim3(grid), dim3(kVoxThreads), 0, c->stream, c->g.N,
-                         (const double*)c->dF64, c->P, c->scale, 1.0 / (double)c->g.N, grad_dev);
-    }
+    HIPCALL(hipMalloc((void**)&grad_dev, (size_t)N * sizeof(double)));
+    e.hdesc[0].out = grad_dev;
+    const hipError_t ue = hipMemcpyAsync(e.ddesc, e.hdesc, sizeof(ProbDesc), hipMemcpyHostToDevice, e.stream);
+    if (ue == hipSuccess)
+      hipLaunchKernelGGL(adjoint_grad_batch, dim3(cl.vb, 1, 1), dim3(kVoxThreads), 0, e.stream, e.ddesc, cl.ids);
     const hipError_t le = hipGetLastError();
-    const hipError_t se = hipStreamSynchronize(c->stream);
-    const hipError_t ce = hipMemcpy(grad_out, grad_dev, (size_t)c->g.N * sizeof(double), hipMemcpyDeviceToHost);
+    const hipError_t se = hipStreamSynchronize(e.stream);
+    const hipError_t ce = hipMemcpy(grad_out, grad_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(grad_dev);
+    e.hdesc[0].out = nullptr;
+    HIPCALL(ue);
     HIPCALL(le);
     HIPCALL(se);
     HIPCALL(ce);
@@ -998,97 +1248,114 @@ int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
 
 int ghom_apply_operator(ghom_ctx* c, const void* v_dev, void* Av_dev) {
   return guard(c, [&]() -> int {
-    require_ready(c);
+    Engine& e = *c->e;
+    check_material(e.P[0]);
     if (!v_dev || !Av_dev || v_dev == Av_dev) fail(GHOM_EINVAL, "bad operator buffers");
-    if (!c->state_valid) constitutive(c);
-    if (c->prec == GHOM_FP64)
-      operator_apply<double>(c, (double*)v_dev, (double*)Av_dev, false, false, nullptr, nullptr);
-    else
-      operator_apply<float>(c, (float*)v_dev, (float*)Av_dev, false, false, nullptr, nullptr);
-    sync(c);
+    refresh_averages(e, 0);
+    e.hdesc[0].in = v_dev;
+    e.hdesc[0].out = Av_dev;
+    e.hdesc[0].active = 1;
+    upload_descs(e);
+    ShapeClass& cl = e.C[e.P[0].cls];
+    if (e.prec == GHOM_FP64) operator_apply<double>(e, cl, ROLE_OP_PLAIN, false);
+    else operator_apply<float>(e, cl, ROLE_OP_PLAIN, false);
+    sync(e);
+    e.hdesc[0].in = nullptr;
+    e.hdesc[0].out = nullptr;
     return GHOM_OK;
   });
 }
 
 int ghom_apply_projection(ghom_ctx* c, const double* in_dev, double* out_dev) {
   return guard(c, [&]() -> int {
-    if (!c->mask_set) fail(GHOM_ESTATE, "no control mask set");
+    Engine& e = *c->e;
+    if (!e.P[0].mask_set) fail(GHOM_ESTATE, "no control mask set");
     if (!in_dev || !out_dev) fail(GHOM_EINVAL, "null buffer");
-    project64<double>(c, in_dev, out_dev, 1.0, nullptr, false, "proj");
-    sync(c);
+    e.hdesc[0].in = in_dev;
+    e.hdesc[0].out = out_dev;
+    e.hdesc[0].active = 1;
+    upload_descs(e);
+    project64(e, e.C[e.P[0].cls], ROLE_PROJ, "proj");
+    sync(e);
+    e.hdesc[0].in = nullptr;
+    e.hdesc[0].out = nullptr;
     return GHOM_OK;
   });
 }
 
 int ghom_residual(ghom_ctx* c, const double Pbar[9], double* out_dev) {
   return guard(c, [&]() -> int {
-    require_ready(c);
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    check_material(q);
     if (!Pbar || !out_dev) fail(GHOM_EINVAL, "null argument");
-    double pb[9];
-    for (int i = 0; i < 9; ++i) pb[i] = c->mask[i] ? Pbar[i] : 0.0;
-    constitutive(c);
-    project64<double>(c, c->P, out_dev, -1.0, pb, false, "res");
-    sync(c);
+    q.state_valid = false;
+    refresh_averages(e, 0);
+    double* b_keep = e.hdesc[0].b;
+    for (int i = 0; i < 9; ++i) e.hdesc[0].pbar[i] = q.mask[i] ? Pbar[i] : 0.0;
+    e.hdesc[0].b = out_dev;
+    e.hdesc[0].active = 1;
+    upload_descs(e);
+    project64(e, e.C[q.cls], ROLE_RESID, "res");
+    sync(e);
+    e.hdesc[0].b = b_keep;
+    upload_descs(e);
     return GHOM_OK;
   });
+}
+
+static int set_option(Engine& e, int key, int value) {
+  if (key == GHOM_OPT_XPROJ_F64 || key == GHOM_OPT_XPROJ_F32) {
+    if (value < XPROJ_TUNED || value > XPROJ_GROUPS) fail(GHOM_EINVAL, "x-pass variant must be 0, 1 or 2");
+    for (auto& cl : e.C) {
+      cl.xproj_var[key == GHOM_OPT_XPROJ_F64 ? 0 : 1] = value;
+      if (value == XPROJ_TUNED) tune_class(e, cl, key == GHOM_OPT_XPROJ_F64 ? 0 : 1);
+    }
+    return GHOM_OK;
+  }
+  if (key == GHOM_OPT_ZSLABS) {
+    if (value < 1 || value > 4096) fail(GHOM_EINVAL, "slab count must be in [1, 4096]");
+    e.zslabs = value;
+    return GHOM_OK;
+  }
+  fail(GHOM_EINVAL, "unknown option");
+}
+
+static int get_option(Engine& e, int key, int* value) {
+  if (!value) fail(GHOM_EINVAL, "null output");
+  if (key == GHOM_OPT_XPROJ_F64) *value = e.C[0].xproj_var[0];
+  else if (key == GHOM_OPT_XPROJ_F32) *value = e.C[0].xproj_var[1];
+  else if (key == GHOM_OPT_ZSLABS) *value = e.zslabs;
+  else fail(GHOM_EINVAL, "unknown option");
+  return GHOM_OK;
 }
 
 int ghom_set_option(ghom_ctx* c, int key, int value) {
-  return guard(c, [&]() -> int {
-    if (key == GHOM_OPT_XPROJ_F64 || key == GHOM_OPT_XPROJ_F32) {
-      if (value < XPROJ_TUNED || value > XPROJ_GROUPS) fail(GHOM_EINVAL, "x-pass variant must be 0, 1 or 2");
-      int& slot = c->xproj_var[key == GHOM_OPT_XPROJ_F64 ? 0 : 1];
-      if (value == XPROJ_TUNED) {
-        slot = XPROJ_TUNED;
-        sync(c);
-        hipLaunchKernelGGL(fill_zero_kernel, dim3(vox_blocks(18 * c->g.Nh)), dim3(kVoxThreads), 0, c->stream,
-                           18 * c->g.Nh, reinterpret_cast<double*>(c->H));
-        HIPCALL(hipGetLastError());
-        if (key == GHOM_OPT_XPROJ_F64) tune_xproj<double>(c);
-        else tune_xproj<float>(c);
-        sync(c);
-      } else {
-        slot = value;
-      }
-      return GHOM_OK;
-    }
-    if (key == GHOM_OPT_ZSLABS) {
-      if (value < 1 || value > 4096) fail(GHOM_EINVAL, "slab count must be in [1, 4096]");
-      c->zslabs = value;
-      return GHOM_OK;
-    }
-    fail(GHOM_EINVAL, "unknown option");
-  });
+  return guard(c, [&]() -> int { return set_option(*c->e, key, value); });
 }
 
 int ghom_get_option(ghom_ctx* c, int key, int* value) {
-  return guard(c, [&]() -> int {
-    if (!value) fail(GHOM_EINVAL, "null output");
-    if (key == GHOM_OPT_XPROJ_F64) *value = c->xproj_var[0];
-    else if (key == GHOM_OPT_XPROJ_F32) *value = c->xproj_var[1];
-    else if (key == GHOM_OPT_ZSLABS) *value = c->zslabs;
-    else fail(GHOM_EINVAL, "unknown option");
-    return GHOM_OK;
-  });
+  return guard(c, [&]() -> int { return get_option(*c->e, key, value); });
 }
 
 int ghom_set_profiling(ghom_ctx* c, int on) {
   return guard(c, [&]() -> int {
-    c->prof = on != 0;
+    c->e->prof = on != 0;
     return GHOM_OK;
   });
 }
 
 int ghom_profile_count(ghom_ctx* c) {
-  if (!c) return GHOM_EINVAL;
-  return (int)c->prof_recs.size();
+  if (!c || !c->e) return GHOM_EINVAL;
+  return (int)c->e->prof_recs.size();
 }
 
 int ghom_profile_get(ghom_ctx* c, int i, char* name_out, int name_cap, int* launches, double* total_ms) {
   return guard(c, [&]() -> int {
-    if (i < 0 || i >= (int)c->prof_recs.size()) fail(GHOM_EINVAL, "record index out of range");
-    prof_collect(c);
-    auto it = c->prof_recs.begin();
+    Engine& e = *c->e;
+    if (i < 0 || i >= (int)e.prof_recs.size()) fail(GHOM_EINVAL, "record index out of range");
+    prof_collect(e);
+    auto it = e.prof_recs.begin();
     std::advance(it, i);
     if (name_out && name_cap > 0) {
       std::strncpy(name_out, it->first.c_str(), (size_t)name_cap - 1);
@@ -1102,10 +1369,153 @@ int ghom_profile_get(ghom_ctx* c, int i, char* name_out, int name_cap, int* laun
 
 int ghom_profile_reset(ghom_ctx* c) {
   return guard(c, [&]() -> int {
-    prof_collect(c);
-    c->prof_recs.clear();
+    prof_collect(*c->e);
+    c->e->prof_recs.clear();
     return GHOM_OK;
   });
+}
+
+// =====================================================================================
+// Batch of independent problems
+// =====================================================================================
+int ghom_batch_create(ghom_batch** out, const ghom_problem* probs, int nprob, int precision, int device,
+                      void* hip_stream) {
+  if (!out) return GHOM_EINVAL;
+  *out = nullptr;
+  if (!probs || nprob < 1 || nprob > 65535) return GHOM_EINVAL;
+  if (precision != GHOM_FP64 && precision != GHOM_FP32_SPLIT) return GHOM_EINVAL;
+  for (int i = 0; i < nprob; ++i) {
+    const ghom_problem& p = probs[i];
+    if (!supported_length(p.nx) || !supported_length(p.ny) || !supported_length(p.nz)) return GHOM_EINVAL;
+    if (!p.phase || p.nphase < 1 || p.nphase > 65536 || p.nsteps < 1 || !p.target) return GHOM_EINVAL;
+    if (p.kind == GHOM_MATERIAL_NEOHOOKEAN) {
+      if (!p.mu || !p.lambda) return GHOM_EINVAL;
+    } else if (p.kind == GHOM_MATERIAL_SVK) {
+      if (!p.C) return GHOM_EINVAL;
+    } else {
+      return GHOM_EINVAL;
+    }
+    for (int c = 0; c < 9; ++c)
+      if (p.mask[c] > 1) return GHOM_EINVAL;
+  }
+  Engine* e = new_engine(precision, device, hip_stream);
+  if (!e) return GHOM_ENOMEM;
+  const int rc = guarded(e, [&]() -> int {
+    open_stream(*e, hip_stream);
+    std::vector<ProbSpec> specs(nprob);
+    std::vector<int> kinds(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      specs[i] = ProbSpec{probs[i].nx, probs[i].ny, probs[i].nz, {1.0, 1.0, 1.0}};
+      kinds[i] = probs[i].kind == GHOM_MATERIAL_NEOHOOKEAN ? MAT_NH : MAT_SVK;
+    }
+    build_engine(*e, specs, kinds);
+    for (int i = 0; i < nprob; ++i) {
+      const ghom_problem& p = probs[i];
+      std::vector<double> tab;
+      if (kinds[i] == MAT_NH) {
+        tab.resize(2 * (size_t)p.nphase);
+        for (int k = 0; k < p.nphase; ++k) {
+          tab[2 * k] = p.mu[k];
+          tab[2 * k + 1] = p.lambda[k];
+        }
+      } else {
+        tab = voigt_table(p.C, p.nphase);
+      }
+      set_material(*e, i, kinds[i], p.phase, p.nphase, tab);
+      Prob& q = e->P[i];
+      unsigned bits = 0;
+      for (int c = 0; c < 9; ++c) {
+        q.mask[c] = p.mask[c];
+        if (p.mask[c]) bits |= 1u << c;
+      }
+      e->hdesc[i].mask = bits;
+      q.mask_set = true;
+      q.target.assign(p.target, p.target + 9 * (size_t)p.nsteps);
+      q.nsteps = p.nsteps;
+    }
+    upload_descs(*e);
+    return GHOM_OK;
+  });
+  ghom_batch* b = rc == GHOM_OK ? new (std::nothrow) ghom_batch() : nullptr;
+  if (!b) {
+    destroy_engine(e);
+    return rc != GHOM_OK ? rc : GHOM_ENOMEM;
+  }
+  b->e = e;
+  *out = b;
+  return GHOM_OK;
+}
+
+void ghom_batch_destroy(ghom_batch* b) {
+  if (!b) return;
+  destroy_engine(b->e);
+  delete b;
+}
+
+const char* ghom_batch_last_error(const ghom_batch* b) { return b && b->e ? b->e->err.c_str() : "null batch"; }
+
+int ghom_batch_set_tolerances(ghom_batch* b, double newton_tol, double cg_tol, double cg_forcing, int max_newton,
+                              int max_cg) {
+  return guard(b, [&]() -> int { return set_tolerances(*b->e, newton_tol, cg_tol, cg_forcing, max_newton, max_cg); });
+}
+
+int ghom_batch_step(ghom_batch* b, ghom_step_info* info) {
+  return guard(b, [&]() -> int {
+    Engine& e = *b->e;
+    std::vector<int> set;
+    for (size_t p = 0; p < e.P.size(); ++p)
+      if (e.P[p].k < e.P[p].nsteps) set.push_back((int)p);
+    if (set.empty()) fail(GHOM_ESTATE, "every history is exhausted");
+    begin_increment(e, set);
+    newton(e, set);
+    int rc = GHOM_OK;
+    std::vector<char> in(e.P.size(), 0);
+    for (int p : set) in[p] = 1;
+    for (size_t p = 0; p < e.P.size(); ++p) {
+      Prob& q = e.P[p];
+      if (in[p] && (q.status == GHOM_OK || q.status == GHOM_ENOTCONVERGED)) q.k += 1;
+      if (info) {
+        info[p] = in[p] ? q.info : ghom_step_info{};
+        if (!in[p]) info[p].status = GHOM_ESTATE;
+      }
+      if (in[p] && q.status != GHOM_OK && rc == GHOM_OK) {
+        rc = q.status;
+        e.err = "problem " + std::to_string(p) + ": " + q.msg;
+      }
+    }
+    return rc;
+  });
+}
+
+int ghom_batch_get_averages(ghom_batch* b, int iprob, double Fbar[9], double Pbar[9]) {
+  return guard(b, [&]() -> int {
+    Engine& e = *b->e;
+    if (iprob < 0 || iprob >= (int)e.P.size() || !Fbar || !Pbar) fail(GHOM_EINVAL, "bad problem index or output");
+    refresh_averages(e, iprob);
+    for (int i = 0; i < 9; ++i) {
+      Fbar[i] = e.P[iprob].Favg[i];
+      Pbar[i] = e.P[iprob].Pavg[i];
+    }
+    return GHOM_OK;
+  });
+}
+
+int ghom_batch_get_field(ghom_batch* b, int iprob, int which, double* host_out) {
+  return guard(b, [&]() -> int {
+    Engine& e = *b->e;
+    if (iprob < 0 || iprob >= (int)e.P.size() || !host_out) fail(GHOM_EINVAL, "bad problem index or output");
+    copy_field(e, iprob, which, host_out, hipMemcpyDeviceToHost);
+    return GHOM_OK;
+  });
+}
+
+int ghom_batch_set_option(ghom_batch* b, int key, int value) {
+  return guard(b, [&]() -> int { return set_option(*b->e, key, value); });
+}
+
+int ghom_batch_num_classes(ghom_batch* b) {
+  if (!b || !b->e) return GHOM_EINVAL;
+  return (int)b->e->C.size();
 }
 
 }  // extern "C"

@@ -192,8 +192,8 @@ __device__ __forceinline__ void four_step_second_inv(const cx<T>* v, int q, cons
 // y pass: in-place complex transform along y of every spectrum line (c, x, kz)
 // ---------------------------------------------------------------------------------
 template <typename T, int A, int B, int DIR>
-__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-ypass_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, const CGScalars* __restrict__ sc) {
+__device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw,
+                                           const CGScalars* __restrict__ sc, int bx) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -202,7 +202,7 @@ ypass_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw
   const int j = threadIdx.x % TC;
   const int q = threadIdx.x / TC;
   const long long ncols = 9LL * g.nx * sl.nkz;
-  const long long col = (long long)blockIdx.x * TC + j;
+  const long long col = (long long)bx * TC + j;
   const bool ok = col < ncols;
   const long long grp = col / sl.nkz;  // (c, x)
   const long long base = grp * ((long long)g.ny * g.nzh) + sl.kz0 + (col - grp * sl.nkz);
@@ -262,9 +262,9 @@ template <typename T, int A, int B> struct XCfg {
 };
 
 template <typename T, int A, int B>
-__global__ void __launch_bounds__((XCfg<T, A, B>::NT))
-xproj_groups_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
-             const CGScalars* __restrict__ sc) {
+__device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
+                                                  const cx<T>* __restrict__ tw, const ProjParams& pp,
+                                                  const CGScalars* __restrict__ sc, int bx, int by) {
   using Cfg = XCfg<T, A, B>;
   constexpr int TC = Cfg::TC, RS = Cfg::RS, REG = Cfg::REG;
   __shared__ cx<T> lds[3 * REG];
@@ -273,11 +273,11 @@ xproj_groups_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restri
   const int tl = threadIdx.x - l * Cfg::NG;
   const int j = tl % TC;
   const int q = tl / TC;
-  const int row = blockIdx.y;
+  const int row = by;
   const int comp = 3 * row + l;
   cx<T>* E = lds + l * REG;                     // this group's exchange region
   const long long ncols = (long long)g.ny * sl.nkz;
-  const long long col = (long long)blockIdx.x * TC + j;  // column (ky, kz - kz0) of the slab
+  const long long col = (long long)bx * TC + j;  // column (ky, kz - kz0) of the slab
   const bool ok = col < ncols;
   const long long rs = (long long)g.ny * g.nzh;  // stride between x rows
   const int ky = ok ? (int)(col / sl.nkz) : 0;
@@ -334,9 +334,9 @@ xproj_groups_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restri
 // Variant "rows": one thread transforms all three components of its columns in turn and
 // carries only the scalar s between the forward and the inverse transforms.
 template <typename T, int A, int B>
-__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-xproj_rows_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw, ProjParams pp,
-             const CGScalars* __restrict__ sc) {
+__device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
+                                                const cx<T>* __restrict__ tw, const ProjParams& pp,
+                                                const CGScalars* __restrict__ sc, int bx, int by) {
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -344,9 +344,9 @@ xproj_rows_kernel(Geo g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict
   if (sc && sc->done) return;
   const int j = threadIdx.x % TC;
   const int q = threadIdx.x / TC;
-  const int row = blockIdx.y;  // tensor row i: components 3i, 3i+1, 3i+2
+  const int row = by;  // tensor row i: components 3i, 3i+1, 3i+2
   const long long ncols = (long long)g.ny * sl.nkz;
-  const long long col = (long long)blockIdx.x * TC + j;  // column (ky, kz - kz0) of the slab
+  const long long col = (long long)bx * TC + j;  // column (ky, kz - kz0) of the slab
   const bool ok = col < ncols;
   const long long rs = (long long)g.ny * g.nzh;  // stride between x rows
   const int ky = ok ? (int)(col / sl.nkz) : 0;
@@ -494,15 +494,14 @@ struct ZfwdArgs {
 };
 
 template <typename T, int A, int B, int MODE, typename TIN>
-__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
-zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
+__device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& args, int bx) {
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
-  const long long line0 = (long long)blockIdx.x * (2 * LP);
+  const long long line0 = (long long)bx * (2 * LP);
   T* ldsr = reinterpret_cast<T*>(lds);
   double pkp = 0.0;
   const T beta = (MODE != Z_PLAIN && args.update_p) ? (T)args.sc->beta : (T)0;
@@ -593,7 +592,7 @@ zfwd_kernel(Geo g, ZfwdArgs<T, TIN> args) {
   }
   if (args.partials) {
     const double t = block_sum<NT>(pkp, red);
-    if (threadIdx.x == 0) args.partials[blockIdx.x] = t;
+    if (threadIdx.x == 0) args.partials[bx] = t;
   }
 }
 
@@ -614,15 +613,14 @@ struct ZinvArgs {
 };
 
 template <typename T, int A, int B, typename TOUT, bool CGU>
-__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
-zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
+__device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>& args, int bx) {
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
-  const long long line0 = (long long)blockIdx.x * (2 * LP);
+  const long long line0 = (long long)bx * (2 * LP);
   const int nzh = g.nzh;
   // phase 1: Z[k] = A[k] + i B[k] with Hermitian completion; Nyquist (even NZ) is zero
   for (int t = threadIdx.x; t < 9 * LP * nzh; t += NT) {
@@ -687,7 +685,7 @@ zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
   }
   if (CGU || args.dot_with) {
     const double s = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) args.partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) args.partials[bx] = s;
   }
 }
 
@@ -697,17 +695,18 @@ zinv_kernel(Geo g, ZinvArgs<T, TOUT> args) {
 constexpr int kVoxThreads = 256;
 
 template <typename TS, int KIND>
-__global__ void __launch_bounds__(kVoxThreads)
-constitutive_kernel(Geo g, const double* __restrict__ F, double* __restrict__ P, TS* __restrict__ state,
-                    const uint16_t* __restrict__ phase, const double* __restrict__ scale,
-                    const double* __restrict__ mat, double* __restrict__ partials, int* __restrict__ flag) {
+__device__ __forceinline__ void constitutive_body(const Geo& g, const double* __restrict__ F, double* __restrict__ P,
+                                                  TS* __restrict__ state, const uint16_t* __restrict__ phase,
+                                                  const double* __restrict__ scale, const double* __restrict__ mat,
+                                                  double* __restrict__ partials, int* __restrict__ flag, int bx,
+                                                  int gx) {
   __shared__ double red[kVoxThreads / 64];
   double sums[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) sums[k] = 0.0;
   int bad = 0;
-  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < g.N;
-       v += (long long)gridDim.x * kVoxThreads) {
+  for (long long v = (long long)bx * kVoxThreads + threadIdx.x; v < g.N;
+       v += (long long)gx * kVoxThreads) {
     double f[9], p[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) f[c] = F[c * g.N + v];
@@ -782,7 +781,7 @@ constitutive_kernel(Geo g, const double* __restrict__ F, double* __restrict__ P,
 #pragma unroll
   for (int k = 0; k < 18; ++k) {
     const double s = block_sum<kVoxThreads>(sums[k], red);
-    if (threadIdx.x == 0) partials[(long long)blockIdx.x * 18 + k] = s;
+    if (threadIdx.x == 0) partials[(long long)bx * 18 + k] = s;
   }
 }
 
@@ -791,12 +790,12 @@ constitutive_kernel(Geo g, const double* __restrict__ F, double* __restrict__ P,
 // ---------------------------------------------------------------------------------
 // x = 0, r = (T) b, p = r, partial r.r
 template <typename T>
-__global__ void __launch_bounds__(kVoxThreads)
-cg_init_kernel(long long n, const double* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
-               T* __restrict__ p, double* __restrict__ partials) {
+__device__ __forceinline__ void cg_init_body(long long n, const double* __restrict__ b, T* __restrict__ x,
+                                             T* __restrict__ r, T* __restrict__ p, double* __restrict__ partials,
+                                             int bx, int gx) {
   __shared__ double red[kVoxThreads / 64];
   double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kVoxThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVoxThreads) {
+  for (long long i = (long long)bx * kVoxThreads + threadIdx.x; i < n; i += (long long)gx * kVoxThreads) {
     const T v = (T)b[i];
     x[i] = (T)0;
     r[i] = v;
@@ -804,7 +803,7 @@ cg_init_kernel(long long n, const double* __restrict__ b, T* __restrict__ x, T* 
     acc += (double)v * (double)v;
   }
   const double s = block_sum<kVoxThreads>(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[bx] = s;
 }
 
 // sum of nparts partials in a fixed order, by one block
@@ -816,8 +815,8 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
 }
 
 // which: 0 = start (rr from partials, converged test), 1 = alpha (pAp), 2 = beta (rr_new)
-__global__ void __launch_bounds__(kRedThreads)
-cg_scalar_kernel(CGScalars* sc, const double* __restrict__ partials, int nparts, int which) {
+__device__ __forceinline__ void cg_scalar_body(CGScalars* sc, const double* __restrict__ partials, int nparts,
+                                               int which) {
   __shared__ double red[kRedThreads / 64];
   if (which != 0 && sc->done) return;
   const double s = reduce_partials(partials, nparts, 1, 0, red);
@@ -855,8 +854,8 @@ cg_scalar_kernel(CGScalars* sc, const double* __restrict__ partials, int nparts,
 
 // column sums of a (nparts x K) partials table into out[0..K); the first nmax columns
 // are reduced with max instead of sum (one block, fixed order)
-__global__ void __launch_bounds__(kRedThreads)
-sum_columns_kernel(const double* __restrict__ partials, int nparts, int K, int nmax, double* __restrict__ out) {
+__device__ __forceinline__ void sum_columns_body(const double* __restrict__ partials, int nparts, int K, int nmax,
+                                                 double* __restrict__ out) {
   __shared__ double red[kRedThreads / 64];
   for (int k = 0; k < K; ++k) {
     double r;
@@ -873,14 +872,14 @@ sum_columns_kernel(const double* __restrict__ partials, int nparts, int K, int n
 
 // F += dF; partials: max |dF(x)|^2 and sums of F (10 columns)
 template <typename TD>
-__global__ void __launch_bounds__(kVoxThreads)
-newton_update_kernel(Geo g, double* __restrict__ F, const TD* __restrict__ dF, double* __restrict__ partials) {
+__device__ __forceinline__ void newton_update_body(const Geo& g, double* __restrict__ F, const TD* __restrict__ dF,
+                                                   double* __restrict__ partials, int bx, int gx) {
   __shared__ double red[kVoxThreads / 64];
   double mx = 0.0;
   double sums[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) sums[c] = 0.0;
-  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < g.N; v += (long long)gridDim.x * kVoxThreads) {
+  for (long long v = (long long)bx * kVoxThreads + threadIdx.x; v < g.N; v += (long long)gx * kVoxThreads) {
     double n2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -893,45 +892,255 @@ newton_update_kernel(Geo g, double* __restrict__ F, const TD* __restrict__ dF, d
     mx = fmax(mx, n2);
   }
   const double m = block_max<kVoxThreads>(mx, red);
-  if (threadIdx.x == 0) partials[(long long)blockIdx.x * 10] = m;
+  if (threadIdx.x == 0) partials[(long long)bx * 10] = m;
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     const double s = block_sum<kVoxThreads>(sums[c], red);
-    if (threadIdx.x == 0) partials[(long long)blockIdx.x * 10 + 1 + c] = s;
+    if (threadIdx.x == 0) partials[(long long)bx * 10 + 1 + c] = s;
   }
 }
 
-struct Shift9 { double d[9]; };
-
-__global__ void __launch_bounds__(kVoxThreads)
-shift_kernel(long long N, double* __restrict__ F, Shift9 s) {
-  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+__device__ __forceinline__ void shift_body(long long N, double* __restrict__ F, const double* s, int bx, int gx) {
+  for (long long v = (long long)bx * kVoxThreads + threadIdx.x; v < N; v += (long long)gx * kVoxThreads) {
 #pragma unroll
     for (int c = 0; c < 9; ++c)
-      if (s.d[c] != 0.0) F[c * N + v] += s.d[c];
+      if (s[c] != 0.0) F[c * N + v] += s[c];
   }
 }
 
 // uniform field value[c] in every voxel (FP64)
-__global__ void __launch_bounds__(kVoxThreads)
-fill9_kernel(long long N, double* __restrict__ out, Shift9 val) {
-  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+__device__ __forceinline__ void fill9_body(long long N, double* __restrict__ out, const double* val, int bx, int gx) {
+  for (long long v = (long long)bx * kVoxThreads + threadIdx.x; v < N; v += (long long)gx * kVoxThreads) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) out[c * N + v] = val.d[c];
+    for (int c = 0; c < 9; ++c) out[c * N + v] = val[c];
   }
 }
 
 // dJ/ds(x) = -(lam(x) : P(x)) / s(x), lam the adjoint field (already divided by N)
 template <typename TL>
-__global__ void __launch_bounds__(kVoxThreads)
-adjoint_grad_kernel(long long N, const TL* __restrict__ lam, const double* __restrict__ P,
-                    const double* __restrict__ scale, double inv_n, double* __restrict__ grad) {
-  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+__device__ __forceinline__ void adjoint_grad_body(long long N, const TL* __restrict__ lam, const double* __restrict__ P,
+                                                  const double* __restrict__ scale, double inv_n,
+                                                  double* __restrict__ grad, int bx, int gx) {
+  for (long long v = (long long)bx * kVoxThreads + threadIdx.x; v < N; v += (long long)gx * kVoxThreads) {
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < 9; ++c) acc += (double)lam[c * N + v] * P[c * N + v];
     grad[v] = -acc * inv_n / (scale ? scale[v] : 1.0);
   }
+}
+
+// =================================================================================
+// Batched launches.  Every pass runs over a set of problems of one grid shape: the
+// problem is blockIdx.z (through `ids`), the tile inside it blockIdx.x (and .y).  A
+// single problem is a batch of one.
+// =================================================================================
+enum {
+  ROLE_OP_CG = 0,     // CG step: zfwd on p (p <- r + beta p), zinv updates x, r
+  ROLE_OP_PLAIN = 1,  // operator on `in`, result to `out`
+  ROLE_RESID = 2,     // -G*(P - P-bar) into b, with b.b partials
+  ROLE_REPROJ = 3,    // G*(x) into dF64 (float64)
+  ROLE_PROJ = 4       // G*(in) into out (float64)
+};
+
+struct ProbDesc {
+  Geo g;
+  int kind;          // MAT_NH or MAT_SVK
+  int has_scale;
+  unsigned mask;     // bit c: component c stress-controlled
+  int active;        // nonzero while this problem takes part in the current solve
+  double pbar[9];    // stress target of the current increment (stress-controlled comps)
+  double shift[9];   // uniform shift of the deformation-controlled means
+  double fill[9];    // value of a uniform fill
+  double cg_thresh;  // CG stop: r.r <= cg_thresh
+  int max_cg;
+  double *F, *P, *b, *dF64;
+  void *x, *r, *p, *state, *H;
+  const uint16_t* phase;
+  const double* scale;
+  const double* mat;
+  const float* mat32;
+  const cx<double>* tw64[3];
+  const cx<float>* tw32[3];
+  double* partials;  // this problem's partial sums
+  CGScalars* sc;
+  double* red;       // reduced values (32)
+  int* flag;         // det F <= 0 flag
+  const void* in;    // ROLE_OP_PLAIN / ROLE_PROJ input
+  void* out;         // ROLE_OP_PLAIN / ROLE_PROJ output; adjoint gradient
+};
+
+template <typename T> __device__ __forceinline__ const cx<T>* twd(const ProbDesc& d, int axis);
+template <> __device__ __forceinline__ const cx<double>* twd<double>(const ProbDesc& d, int axis) { return d.tw64[axis]; }
+template <> __device__ __forceinline__ const cx<float>* twd<float>(const ProbDesc& d, int axis) { return d.tw32[axis]; }
+
+__device__ __forceinline__ ProjParams proj_params(const ProbDesc& d, int role) {
+  ProjParams pp;
+  pp.mask = d.mask;
+  const double n = (double)d.g.N;
+  pp.post = (role == ROLE_RESID ? -1.0 : 1.0) / n;
+  for (int c = 0; c < 9; ++c) pp.off[c] = role == ROLE_RESID ? n * d.pbar[c] : 0.0;
+  return pp;
+}
+
+template <typename T, int A, int B, int MODE, typename TIN>
+__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
+zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, int update_p) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  ZfwdArgs<T, TIN> a{};
+  if constexpr (MODE == Z_PLAIN) {
+    a.in = role == ROLE_RESID ? reinterpret_cast<const TIN*>(d.P)
+                              : (role == ROLE_REPROJ ? reinterpret_cast<const TIN*>(d.x)
+                                                     : reinterpret_cast<const TIN*>(d.in));
+  } else {
+    const bool cg = role == ROLE_OP_CG;
+    a.p = cg ? reinterpret_cast<T*>(d.p) : const_cast<T*>(reinterpret_cast<const T*>(d.in));
+    a.r = reinterpret_cast<const T*>(d.r);
+    a.update_p = cg ? update_p : 0;
+    a.state = reinterpret_cast<const T*>(d.state);
+    a.phase = d.phase;
+    if constexpr (sizeof(T) == 8) a.C6 = reinterpret_cast<const T*>(d.mat);
+    else a.C6 = reinterpret_cast<const T*>(d.mat32);
+    a.has_scale = d.has_scale;
+    a.partials = cg ? d.partials : nullptr;
+    a.sc = cg ? d.sc : nullptr;
+  }
+  a.H = reinterpret_cast<cx<T>*>(d.H);
+  a.tw = twd<T>(d, 2);
+  zfwd_body<T, A, B, MODE, TIN>(d.g, a, blockIdx.x);
+}
+
+template <typename T, int A, int B, int DIR>
+__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
+ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  ypass_body<T, A, B, DIR>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
+                           blockIdx.x);
+}
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
+xproj_rows_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const ProjParams pp = proj_params(d, role);
+  xproj_rows_body<T, A, B>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
+                           role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__((XCfg<T, A, B>::NT))
+xproj_groups_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const ProjParams pp = proj_params(d, role);
+  xproj_groups_body<T, A, B>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
+                             role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int A, int B, typename TOUT, bool CGU>
+__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
+zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  ZinvArgs<T, TOUT> a{};
+  a.H = reinterpret_cast<const cx<T>*>(d.H);
+  a.tw = twd<T>(d, 2);
+  a.partials = d.partials;
+  if constexpr (CGU) {
+    a.x = reinterpret_cast<TOUT*>(d.x);
+    a.r = reinterpret_cast<TOUT*>(d.r);
+    a.p = reinterpret_cast<const TOUT*>(d.p);
+    a.sc = d.sc;
+  } else {
+    a.out = role == ROLE_RESID ? reinterpret_cast<TOUT*>(d.b)
+                               : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
+    a.dot_with = role == ROLE_RESID ? a.out : nullptr;
+  }
+  zinv_body<T, A, B, TOUT, CGU>(d.g, a, blockIdx.x);
+}
+
+template <typename TS, int KIND>
+__global__ void __launch_bounds__(kVoxThreads)
+constitutive_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  constitutive_body<TS, KIND>(d.g, d.F, d.P, reinterpret_cast<TS*>(d.state), d.phase, d.has_scale ? d.scale : nullptr,
+                              d.mat, d.partials, d.flag, blockIdx.x, gridDim.x);
+}
+
+// r = (T) b, x = 0, p = r with r.r partials; the CG scalars are reset for every problem
+// (inactive ones start finished)
+template <typename T>
+__global__ void __launch_bounds__(kVoxThreads)
+cg_init_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.sc->thresh = d.cg_thresh;
+    d.sc->max_it = d.max_cg;
+    d.sc->it = 0;
+    d.sc->done = d.active ? 0 : 1;
+    d.sc->status = d.active ? 0 : 1;
+  }
+  if (!d.active) return;
+  cg_init_body<T>(9 * d.g.N, d.b, reinterpret_cast<T*>(d.x), reinterpret_cast<T*>(d.r), reinterpret_cast<T*>(d.p),
+                  d.partials, blockIdx.x, gridDim.x);
+}
+
+// one block per problem
+__global__ void __launch_bounds__(kRedThreads)
+cg_scalar_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int which) {
+  const ProbDesc& d = D[ids[blockIdx.x]];
+  if (!d.active) return;
+  cg_scalar_body(d.sc, d.partials, nparts, which);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+sum_columns_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int K, int nmax) {
+  const ProbDesc& d = D[ids[blockIdx.x]];
+  if (!d.active) return;
+  sum_columns_body(d.partials, nparts, K, nmax, d.red);
+}
+
+// F += dF with dF the float64 correction: x itself in FP64 mode, the re-projected dF64 in
+// FP32-split mode
+__global__ void __launch_bounds__(kVoxThreads)
+newton_update_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const double* dF = d.dF64 ? d.dF64 : reinterpret_cast<const double*>(d.x);
+  newton_update_body<double>(d.g, d.F, dF, d.partials, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kVoxThreads)
+shift_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  shift_body(d.g.N, d.F, d.shift, blockIdx.x, gridDim.x);
+}
+
+// which: 0 = F (reset to the fill value), 1 = b (uniform right-hand side)
+__global__ void __launch_bounds__(kVoxThreads)
+fill9_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int which) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  fill9_body(d.g.N, which == 0 ? d.F : d.b, d.fill, blockIdx.x, gridDim.x);
+}
+
+__global__ void zero_flag_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *D[ids[i]].flag = 0;
+}
+
+// dJ/ds from the adjoint solution (float64: x in FP64 mode, re-projected dF64 in split mode)
+__global__ void __launch_bounds__(kVoxThreads)
+adjoint_grad_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const double* lam = d.dF64 ? d.dF64 : reinterpret_cast<const double*>(d.x);
+  adjoint_grad_body<double>(d.g.N, lam, d.P, d.has_scale ? d.scale : nullptr, 1.0 / (double)d.g.N,
+                            reinterpret_cast<double*>(d.out), blockIdx.x, gridDim.x);
 }
 
 }  // namespace ghom

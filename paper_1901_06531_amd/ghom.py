@@ -46,6 +46,16 @@ class StepInfo(ctypes.Structure):
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
+MATERIAL_NEOHOOKEAN = 1
+MATERIAL_SVK = 2
+
+
+class Problem(ctypes.Structure):
+    """ghom_problem: one problem of a batch."""
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("kind", ctypes.c_int),
+                ("phase", ctypes.c_void_p), ("nphase", ctypes.c_int), ("mu", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("C", ctypes.c_void_p), ("mask", ctypes.c_uint8 * 9),
+                ("nsteps", ctypes.c_int), ("target", ctypes.c_void_p)]
 _d = ctypes.c_double
 _dp = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
@@ -69,6 +79,15 @@ _SIGS = {
     "ghom_apply_operator": (_i, [_vp, _vp, _vp]),
     "ghom_apply_projection": (_i, [_vp, _vp, _vp]),
     "ghom_residual": (_i, [_vp, _vp, _vp]),
+    "ghom_batch_create": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _vp]),
+    "ghom_batch_destroy": (None, [_vp]),
+    "ghom_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "ghom_batch_set_tolerances": (_i, [_vp, _d, _d, _d, _i, _i]),
+    "ghom_batch_step": (_i, [_vp, _vp]),
+    "ghom_batch_get_averages": (_i, [_vp, _i, _vp, _vp]),
+    "ghom_batch_get_field": (_i, [_vp, _i, _i, _vp]),
+    "ghom_batch_set_option": (_i, [_vp, _i, _i]),
+    "ghom_batch_num_classes": (_i, [_vp]),
     "ghom_set_option": (_i, [_vp, _i, _i]),
     "ghom_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
     "ghom_set_profiling": (_i, [_vp, _i]),
@@ -301,3 +320,95 @@ class Solver:
 
     def profile_reset(self):
         self._check(lib().ghom_profile_reset(self._c))
+
+
+class Batch:
+    """Many independent problems advanced together (a ghom_batch).
+
+    ``workloads`` is a list of dicts as made by paper_1901_06531_amd.synth (shape, kind,
+    phase, mu/lam or C, mask, target)."""
+
+    def __init__(self, workloads, precision=FP32_SPLIT, device=0, stream=None):
+        self.n = len(workloads)
+        self.shapes = [tuple(int(v) for v in w["shape"]) for w in workloads]
+        self._keep = []
+        arr = (Problem * self.n)()
+        for i, w in enumerate(workloads):
+            pr = arr[i]
+            pr.nx, pr.ny, pr.nz = self.shapes[i]
+            ph = np.ascontiguousarray(np.asarray(w["phase"]).reshape(-1), dtype=np.uint16)
+            tgt = np.ascontiguousarray(w["target"], dtype=np.float64).reshape(-1, 9)
+            self._keep += [ph, tgt]
+            pr.phase = ph.ctypes.data
+            pr.target = tgt.ctypes.data
+            pr.nsteps = tgt.shape[0]
+            for c in range(9):
+                pr.mask[c] = int(np.asarray(w["mask"]).reshape(9)[c])
+            if w["kind"] == "nh":
+                mu = np.ascontiguousarray(w["mu"], dtype=np.float64).reshape(-1)
+                lam = np.ascontiguousarray(w["lam"], dtype=np.float64).reshape(-1)
+                self._keep += [mu, lam]
+                pr.kind = MATERIAL_NEOHOOKEAN
+                pr.nphase = len(mu)
+                pr.mu, pr.lam = mu.ctypes.data, lam.ctypes.data
+            else:
+                C = np.ascontiguousarray(w["C"], dtype=np.float64).reshape(-1, 81)
+                self._keep.append(C)
+                pr.kind = MATERIAL_SVK
+                pr.nphase = C.shape[0]
+                pr.C = C.ctypes.data
+        self._b = ctypes.c_void_p()
+        rc = lib().ghom_batch_create(ctypes.byref(self._b), ctypes.cast(arr, ctypes.c_void_p), self.n, int(precision),
+                                     int(device), stream)
+        self._keep = None
+        if rc != 0:
+            raise GhomError(rc, "ghom_batch_create failed")
+
+    def _check(self, rc):
+        if rc != 0:
+            raise GhomError(rc, lib().ghom_batch_last_error(self._b).decode())
+        return rc
+
+    def close(self):
+        if self._b:
+            lib().ghom_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_tolerances(self, newton_tol=1e-6, cg_tol=1e-8, cg_forcing=0.0, max_newton=50, max_cg=5000):
+        self._check(lib().ghom_batch_set_tolerances(self._b, newton_tol, cg_tol, cg_forcing, max_newton, max_cg))
+
+    def set_option(self, key, value):
+        self._check(lib().ghom_batch_set_option(self._b, int(key), int(value)))
+
+    def num_classes(self):
+        return lib().ghom_batch_num_classes(self._b)
+
+    def step(self, raise_on_error=True):
+        infos = (StepInfo * self.n)()
+        rc = lib().ghom_batch_step(self._b, ctypes.cast(infos, ctypes.c_void_p))
+        if raise_on_error:
+            self._check(rc)
+        return [infos[i].as_dict() for i in range(self.n)]
+
+    def averages(self, i):
+        F = np.zeros(9)
+        P = np.zeros(9)
+        self._check(lib().ghom_batch_get_averages(self._b, int(i), _ptr(F), _ptr(P)))
+        return F, P
+
+    def field(self, i, which=FIELD_F):
+        out = np.empty((9,) + self.shapes[i])
+        self._check(lib().ghom_batch_get_field(self._b, int(i), int(which), _ptr(out)))
+        return out

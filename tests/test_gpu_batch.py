@@ -1,0 +1,101 @@
+"""Batched problems: every problem of a batch gets the result it gets alone.
+
+The batch mixes grid shapes, material laws and control masks, so that several launch
+groups run side by side and problems converge after different Newton and CG counts."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ghom_oracle as go  # noqa: E402
+from paper_1901_06531_amd import ghom, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _problems():
+    ws = []
+    g = np.random.default_rng(0)
+    for i, n in enumerate([16, 24, 16, 32, 24, 16]):
+        shape = (n, n, n)
+        centers, radii = synth.rsa_spheres(3 + i % 3, 0.08, 0.15, 100 + i, target_vf=0.15)
+        phase = synth.spheres_phase(shape, centers, radii)
+        c = 5.0 + 3.0 * i
+        if i % 3 == 0:  # uniaxial stress along axis i % 3 (paper case-1 mask), F-ramp
+            mask = synth.mask_uniaxial(i % 3)
+            F_end = np.eye(3)
+            F_end[i % 3, i % 3] = 1.06
+            target = synth.history_mixed(mask, F_end.reshape(9), 3)
+        elif i % 3 == 1:  # simple shear: F12 prescribed, normal stresses free
+            mask = np.zeros(9, np.uint8)
+            mask[[0, 4, 8]] = 1
+            F_end = np.eye(3)
+            F_end[0, 1] = 0.1
+            target = synth.history_mixed(mask, F_end.reshape(9), 3)
+        else:  # full stress control
+            mask = synth.mask_full_stress()
+            P_end = np.zeros(9)
+            P_end[0] = 0.1
+            target = synth.history_stress_ramp(P_end, 3)
+        w = dict(shape=shape, phase=phase, mask=mask, target=target, newton_tol=1e-10, cg_tol=1e-11)
+        if i == 4:  # one Saint Venant-Kirchhoff polycrystal
+            w["phase"] = synth.voronoi_grains(shape, 6, 7)
+            w["kind"] = "svk"
+            w["C"] = synth.rotate_C(synth.cubic_C(1.7, 1.2, 0.75), synth.haar_rotations(6, 8)).reshape(6, 81)
+        else:
+            w["kind"] = "nh"
+            w["mu"] = np.array([1.0, c])
+            w["lam"] = np.array([2.0, 2 * c])
+        ws.append(w)
+    return ws
+
+
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_batch_matches_single_problems(prec):
+    ws = _problems()
+    say("batch of", len(ws), "problems, precision", prec)
+    with ghom.Batch(ws, precision=prec) as b:
+        b.set_tolerances(1e-10, 1e-11, 1e-5 if prec == ghom.FP32_SPLIT else 0.0)
+        assert b.num_classes() == 4  # 16^3 NH, 24^3 NH, 32^3 NH, 24^3 SVK
+        binfo = [b.step() for _ in range(3)]
+        bavg = [b.averages(i) for i in range(len(ws))]
+        bF = [b.field(i) for i in range(len(ws))]
+    for i, w in enumerate(ws):
+        with ghom.Solver(w["shape"], precision=prec) as s:
+            s.setup(w)
+            s.set_tolerances(1e-10, 1e-11, 1e-5 if prec == ghom.FP32_SPLIT else 0.0)
+            sinfo = [s.step() for _ in range(3)]
+            F, P = s.averages()
+            Fs = s.field()
+        say("  problem", i, w["shape"], w["kind"], "newton", [x[i]["newton_iters"] for x in binfo],
+            [x["newton_iters"] for x in sinfo])
+        np.testing.assert_allclose(bavg[i][0], F, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(bavg[i][1], P, rtol=0, atol=1e-12)
+        assert np.max(np.abs(bF[i] - Fs)) < 1e-11
+        assert [x[i]["newton_iters"] for x in binfo] == [x["newton_iters"] for x in sinfo]
+
+
+def test_batch_problem_matches_oracle():
+    """One mixed-control problem of the batch against the FP64 oracle's history."""
+    ws = _problems()
+    with ghom.Batch(ws, precision=ghom.FP64) as b:
+        b.set_tolerances(1e-10, 1e-11)
+        for _ in range(3):
+            b.step()
+        got = [b.averages(i) for i in (0, 1)]
+    for i in (0, 1):
+        w = ws[i]
+        o = go.Oracle(w["shape"])
+        o.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+        o.set_control(w["mask"])
+        o.set_history(w["target"])
+        o.set_tolerances(1e-10, 1e-11)
+        go.run_history(o)
+        F, P = o.averages()
+        np.testing.assert_allclose(got[i][0], F, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(got[i][1], P, rtol=0, atol=1e-10)
