@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CG operator voxel-iters/s + Newton step time at 256^3, FP64 vs FP32-split"
 PEAK_HBM_GBS = 8000.0
+CG_FORCING = 1e-5
 
 
 def log(*a):
@@ -76,8 +77,9 @@ def run_gpu(w, precision, steps, warmup, profile):
     s = ghom.Solver(w["shape"], precision=precision)
     s.setup(w)
     xproj = {"f64": s.get_option(ghom.OPT_XPROJ_F64), "f32": s.get_option(ghom.OPT_XPROJ_F32)}
-    forcing = 0.0
-    s.set_tolerances(w["newton_tol"], w["cg_tol"], forcing)
+    # both precisions stop CG at max(1e-8, 1e-5 |b|): the float32 CG needs the relative
+    # floor, and the float64 run uses the same rule so that the two are compared fairly
+    s.set_tolerances(w["newton_tol"], w["cg_tol"], CG_FORCING)
     for i in range(warmup):
         info = s.step()
         log("  warmup increment %d: newton %d cg %d  %.1f ms" % (i + 1, info["newton_iters"], info["cg_iters_total"],
@@ -113,6 +115,67 @@ def run_gpu(w, precision, steps, warmup, profile):
         "P11": float(P[0]),
         "xproj_variant": xproj,
     }, prof
+
+
+def run_batch(steps, warmup, sample_per_size=2):
+    """The batched workload: 64 RVEs (16 each of 32^3, 48^3, 64^3, 96^3) x 6 load cases = 384
+    problems advanced together (FP32-split), one increment per step; beside it a sample of the
+    same problems run one at a time through single-problem contexts."""
+    from paper_1901_06531_amd import ghom, synth
+
+    t0 = time.perf_counter()
+    ws = synth.workload_batch()
+    log("batch workload: %d problems, %.1f M voxels, built in %.1f s" % (
+        len(ws), sum(int(np.prod(w["shape"])) for w in ws) / 1e6, time.perf_counter() - t0))
+    import torch
+    t0 = time.perf_counter()
+    b = ghom.Batch(ws, precision=ghom.FP32_SPLIT)
+    b.set_tolerances(1e-6, 1e-8, CG_FORCING)
+    log("batch created in %.1f s (%d launch groups)" % (time.perf_counter() - t0, b.num_classes()))
+    for i in range(warmup):
+        t0 = time.perf_counter()
+        b.step()
+        log("  batch warmup increment %d: %.1f ms" % (i + 1, 1e3 * (time.perf_counter() - t0)))
+    torch.cuda.synchronize()
+    vox_its = 0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        infos = b.step()
+        vox_its += sum(int(np.prod(w["shape"])) * inf["cg_iters_total"] for w, inf in zip(ws, infos))
+        log("  batch timed increment %d: max newton %d, CG iterations %d..%d" % (
+            warmup + i + 1, max(x["newton_iters"] for x in infos), min(x["cg_iters_total"] for x in infos),
+            max(x["cg_iters_total"] for x in infos)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.close()
+    # the same kind of problems one at a time (sample: the first load case of the first
+    # `sample_per_size` RVEs of every size), same precision and tolerances
+    seen = {}
+    sample = []
+    for w in ws:
+        n = w["shape"][0]
+        if w["name"].endswith("uniaxial_x") and seen.get(n, 0) < sample_per_size:
+            seen[n] = seen.get(n, 0) + 1
+            sample.append(w)
+    s_vox = 0
+    s_wall = 0.0
+    for w in sample:
+        with ghom.Solver(w["shape"], precision=ghom.FP32_SPLIT) as s:
+            s.setup(w)
+            s.set_tolerances(1e-6, 1e-8, CG_FORCING)
+            for _ in range(warmup):
+                s.step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                inf = s.step()
+                s_vox += int(np.prod(w["shape"])) * inf["cg_iters_total"]
+            torch.cuda.synchronize()
+            s_wall += time.perf_counter() - t1
+    return {"problems": len(ws), "launch_groups": 4, "increments_timed": steps,
+            "voxel_iters_per_s": round(vox_its / wall, 1), "ms_per_increment": round(1e3 * wall / steps, 1),
+            "one_at_a_time_voxel_iters_per_s": round(s_vox / s_wall, 1),
+            "one_at_a_time_sample": "%d problems (%d per grid size), same increments" % (len(sample), sample_per_size)}
 
 
 def cpu_baseline(w, max_seconds=30.0):
@@ -153,6 +216,7 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 384-problem workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (5 times): the reference for HBM counters")
     args = ap.parse_args()
@@ -207,6 +271,11 @@ def main():
         log("kernel times (timed region): " + ", ".join("%s %.3f ms x%d" % (k, v[1] / v[0], v[0])
                                                         for k, v in sorted(op.items())))
 
+    batch = None
+    if not args.no_batch:
+        log("batched workload")
+        batch = run_batch(1, 1)
+
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
@@ -230,7 +299,7 @@ def main():
         "config": {"workload": w["name"], "grid": list(w["shape"]), "grains": 512, "material": "svk-cubic",
                    "control": "full stress, P11 triangle +-0.02 over 40 increments",
                    "step": "one load increment", "precision": "fp32-split",
-                   "newton_tol": w["newton_tol"], "cg_tol": w["cg_tol"]},
+                   "newton_tol": w["newton_tol"], "cg_tol": w["cg_tol"], "cg_forcing": CG_FORCING},
         "newton_step_ms": round(split["newton_step_ms"], 3),
         "cg_ms_per_iter": round(split["cg_ms_per_iter"], 4),
         "cg_iters": split["cg_iters"],
@@ -241,6 +310,7 @@ def main():
             "newton_step_ms": round(fp64["newton_step_ms"], 3), "cg_ms_per_iter": round(fp64["cg_ms_per_iter"], 4),
             "cg_iters": fp64["cg_iters"], "newton_iters": fp64["newton_iters"],
             "split_vs_fp64_F11_diff": abs(fp64["F11"] - split["F11"])},
+        "batch": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -38,7 +38,11 @@ typedef struct ghom_ctx ghom_ctx;
  *  GHOM_FP64       : everything in float64.
  *  GHOM_FP32_SPLIT : CG vectors, tangent state and the transforms inside CG in float32
  *                    with float64 dot products; F, P, the Newton residual, the averages
- *                    and a float64 re-projection of every Newton correction in float64. */
+ *                    and a float64 re-projection of every Newton correction in float64.
+ *                    Each CG solve stops no tighter than 1e-5 of its right-hand side (the
+ *                    cg_forcing of ghom_set_tolerances is raised to 1e-5 at least): float32
+ *                    CG cannot go much further, and the float64 Newton iteration reaches
+ *                    the Newton tolerance regardless. */
 enum { GHOM_FP64 = 0, GHOM_FP32_SPLIT = 1 };
 
 enum {

@@ -505,6 +505,14 @@ void newton_update(Engine& e, std::vector<double>& crit) {
   }
 }
 
+// Relative CG forcing.  Float32 CG cannot take its residual much below 1e-6 of the
+// right-hand side, so in FP32-split mode the stop is never tighter than 1e-5 of it; the
+// float64 Newton residual still drives the solution to the Newton tolerance.
+constexpr double kSplitMinForcing = 1e-5;
+double forcing(const Engine& e) {
+  return e.prec == GHOM_FP32_SPLIT ? std::max(e.cg_forcing, kSplitMinForcing) : e.cg_forcing;
+}
+
 void set_active_from_running(Engine& e, const std::vector<int>& set) {
   for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
   for (int p : set) e.hdesc[p].active = e.P[p].running ? 1 : 0;
@@ -550,7 +558,7 @@ void newton(Engine& e, const std::vector<int>& set) {
         q.status = GHOM_OK;
         q.running = false;
       } else {
-        const double tol = std::max(e.cg_tol, e.cg_forcing * q.rms_b);
+        const double tol = std::max(e.cg_tol, forcing(e) * q.rms_b);
         e.hdesc[p].cg_thresh = tol * tol * (double)e.C[q.cls].g.N;
         e.hdesc[p].max_cg = e.max_cg;
       }
@@ -1214,7 +1222,7 @@ int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
     refresh_averages(e, 0);
     ShapeClass& cl = e.C[q.cls];
     e.hdesc[0].active = 1;
-    const double tol = std::max(e.cg_tol, e.cg_forcing * std::sqrt(rr));
+    const double tol = std::max(e.cg_tol, forcing(e) * std::sqrt(rr));
     e.hdesc[0].cg_thresh = tol * tol * (double)N;
     e.hdesc[0].max_cg = e.max_cg;
     upload_descs(e);

@@ -49,7 +49,6 @@ def spheres_phase(shape, centers, radii) -> np.ndarray:
     X, Y, Z = voxel_centers(shape)
     phase = np.zeros(shape, dtype=np.uint16)
     for c, r in zip(centers, radii):
-        # restrict the work to the bounding slab along x to keep large grids cheap
         inside = _periodic_sq_dist(X, Y, Z, c) < r * r
         phase[inside] = 1
     return phase
@@ -300,3 +299,51 @@ def workload_adjoint(n=128, seed_geo=1, seed_s=5, nsteps=10):
         mask=mask_full_stress(), target=history_stress_ramp(P_end, nsteps),
         newton_tol=1e-10, cg_tol=1e-12)
     return base
+
+
+def mask_normal_stress_free():
+    """Every off-diagonal F component prescribed, the three normal stresses free (P_ii = 0):
+    the simple-shear control (the sheared plane is set by the F history)."""
+    m = np.zeros(9, dtype=np.uint8)
+    for d in range(3):
+        m[4 * d] = 1
+    return m
+
+
+def workload_batch(sizes=(32, 48, 64, 96), per_size=16, nsteps=10, seed0=100):
+    """Batch of RVEs under six load cases each.
+
+    Each RVE (per_size of every size, seeds seed0 + index) holds U{4..12} random
+    non-overlapping spheres scaled to volume fraction 0.20, neo-Hookean matrix (1, 2) and
+    inclusions c (1, 2) with contrast c ~ U[5, 20].  Load cases: uniaxial along x, y, z
+    (the paper's case-(1) pattern permuted, F_aa -> 1.10) and simple shear in xy, yz, zx
+    (F_ab -> 0.20), each over ``nsteps`` increments.  Returns a list of workload dicts (the
+    phase map is shared by the six cases of an RVE)."""
+    out = []
+    idx = 0
+    for n in sizes:
+        for _ in range(per_size):
+            g = rng(seed0 + idx)
+            count = int(g.integers(4, 13))
+            c = float(g.uniform(5.0, 20.0))
+            centers, radii = rsa_spheres(count, 0.05, 0.10, seed0 + idx, target_vf=0.20)
+            shape = (n, n, n)
+            phase = spheres_phase(shape, centers, radii)
+            mu = np.array([1.0, c])
+            lam = np.array([2.0, 2.0 * c])
+            cases = []
+            for a in range(3):
+                mask = mask_uniaxial(a)
+                F_end = np.eye(3)
+                F_end[a, a] = 1.10
+                cases.append(("uniaxial_%s" % "xyz"[a], mask, history_mixed(mask, F_end.reshape(9), nsteps)))
+            for a, b in ((0, 1), (1, 2), (2, 0)):
+                mask = mask_normal_stress_free()
+                F_end = np.eye(3)
+                F_end[a, b] = 0.20
+                cases.append(("shear_%s%s" % ("xyz"[a], "xyz"[b]), mask, history_mixed(mask, F_end.reshape(9), nsteps)))
+            for name, mask, target in cases:
+                out.append(dict(name="rve%d_%d_%s" % (idx, n, name), shape=shape, kind="nh", phase=phase, mu=mu,
+                                lam=lam, mask=mask, target=target, newton_tol=1e-6, cg_tol=1e-8))
+            idx += 1
+    return out
