@@ -38,7 +38,7 @@ def op_bytes(name, N, Nh, w, svk=True, update_p=True):
     if "yfwd" in name or "yinv" in name or "xproj" in name:
         return 2 * spec
     if "zfwd" in name:
-        state = (15 if svk else 12) * N * w + (2 * N if svk else 0)  # SVK: F, S (no scale plane)
+        state = (9 if svk else 12) * N * w + (2 * N if svk else 0)  # SVK: H = F - I (no scale plane), phase
         # CG step: r, p in, p out (p = r + beta p folded in)
         return field * (3 if update_p else 1) + state + spec
     if "zinv" in name:  # CG step: spectrum, x, r, p in; x, r out

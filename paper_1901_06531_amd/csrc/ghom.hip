@@ -103,7 +103,8 @@ struct Engine {
   CGScalars* sc = nullptr;    // device, one per problem
   double* red = nullptr;      // device, 32 per problem
   int* flags = nullptr;       // device, one per problem
-  CGScalars* host_sc = nullptr;
+  CGScalars* host_sc = nullptr;  // two slots of one entry per problem (slot 0 = latest after a solve)
+  hipEvent_t sc_ev[2] = {nullptr, nullptr};
   double* host_red = nullptr;
   int* host_flags = nullptr;
   double newton_tol = 1e-6, cg_tol = 1e-8, cg_forcing = 0.0;
@@ -451,11 +452,15 @@ void cg_solve(Engine& e, double* t_ms) {
       hipLaunchKernelGGL(cg_scalar_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 0);
     });
   }
+  // The host reads the device-side stop flags one chunk behind: while it waits for the
+  // status copied after chunk k, chunk k+1 is already queued, so the GPU never idles on the
+  // round trip.  Iterations queued after every problem has stopped find their done flag set
+  // and return at once; they change nothing.
   int enqueued = 0;
   int chunk = vox >= (1LL << 21) ? 1 : (vox >= (1LL << 18) ? 2 : 8);
   const size_t n = e.P.size();
-  for (;;) {
-    for (int i = 0; i < chunk; ++i, ++enqueued) {
+  auto enqueue_chunk = [&](int k) {
+    for (int i = 0; i < k; ++i, ++enqueued) {
       for (auto& c : e.C) {
         if (!class_active(e, c)) continue;
         const int gz = operator_apply<T>(e, c, ROLE_OP_CG, enqueued > 0);
@@ -465,14 +470,31 @@ void cg_solve(Engine& e, double* t_ms) {
         });
       }
     }
-    HIPCALL(hipMemcpyAsync(e.host_sc, e.sc, n * sizeof(CGScalars), hipMemcpyDeviceToHost, e.stream));
-    sync(e);
-    bool all = true;
+  };
+  auto post_status = [&](int slot) {
+    HIPCALL(hipMemcpyAsync(e.host_sc + slot * n, e.sc, n * sizeof(CGScalars), hipMemcpyDeviceToHost, e.stream));
+    HIPCALL(hipEventRecord(e.sc_ev[slot], e.stream));
+  };
+  auto all_done = [&](int slot) {
+    HIPCALL(hipEventSynchronize(e.sc_ev[slot]));
     for (size_t p = 0; p < n; ++p)
-      if (e.hdesc[p].active && !e.host_sc[p].done) all = false;
-    if (all) break;
+      if (e.hdesc[p].active && !e.host_sc[slot * n + p].done) return false;
+    return true;
+  };
+  enqueue_chunk(chunk);
+  post_status(0);
+  int slot = 0;
+  for (;;) {
     if (chunk < 8 && vox < (1LL << 21)) chunk *= 2;
+    enqueue_chunk(chunk);
+    post_status(1 - slot);
+    if (all_done(slot)) break;
+    slot = 1 - slot;
   }
+  // the copy behind the last queued chunk holds the same (final) values; wait for it so
+  // that no copy into the slots is in flight when the caller reads slot 0
+  HIPCALL(hipEventSynchronize(e.sc_ev[1 - slot]));
+  if (slot != 0) std::copy(e.host_sc + n, e.host_sc + 2 * n, e.host_sc);
   if (t_ms) *t_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -731,6 +753,8 @@ void destroy_engine(Engine* e) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : e->sc_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
   delete e;
 }
@@ -785,7 +809,7 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
     b += 3 * align256(9 * N * 8);                                       // F, P, b
     if (e.prec == GHOM_FP32_SPLIT) b += align256(9 * N * 8);            // dF64
     b += 3 * align256(9 * N * e.tsz);                                   // x, r, p
-    b += align256((size_t)kSVKState * N * e.tsz);                       // state
+    b += align256((size_t)kStatePlanes * N * e.tsz);                    // state (either law)
     b += align256(9 * (size_t)g.Nh * sizeof(cx<double>));               // spectrum
     b += align256(N * sizeof(uint16_t));                                // phase
     b += align256(np * sizeof(double));                                 // partials
@@ -803,7 +827,8 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   HIPCALL(hipMalloc((void**)&e.red, n * 32 * sizeof(double)));
   HIPCALL(hipMalloc((void**)&e.flags, n * sizeof(int)));
   HIPCALL(hipHostMalloc((void**)&e.hdesc, n * sizeof(ProbDesc), hipHostMallocDefault));
-  HIPCALL(hipHostMalloc((void**)&e.host_sc, n * sizeof(CGScalars), hipHostMallocDefault));
+  HIPCALL(hipHostMalloc((void**)&e.host_sc, 2 * n * sizeof(CGScalars), hipHostMallocDefault));
+  for (auto& ev : e.sc_ev) HIPCALL(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   HIPCALL(hipHostMalloc((void**)&e.host_red, n * 32 * sizeof(double), hipHostMallocDefault));
   HIPCALL(hipHostMalloc((void**)&e.host_flags, n * sizeof(int), hipHostMallocDefault));
   // twiddles W_n^k = exp(-2 pi i k / n) and device id lists per class
@@ -846,7 +871,7 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
     d.x = take(9 * N * e.tsz);
     d.r = take(9 * N * e.tsz);
     d.p = take(9 * N * e.tsz);
-    d.state = take((size_t)kSVKState * N * e.tsz);
+    d.state = take((size_t)kStatePlanes * N * e.tsz);
     d.H = take(9 * (size_t)c.g.Nh * sizeof(cx<double>));
     d.phase = (const uint16_t*)take(N * sizeof(uint16_t));
     d.partials = (double*)take(np * sizeof(double));

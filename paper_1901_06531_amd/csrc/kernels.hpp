@@ -39,7 +39,8 @@ struct Slab {
 
 enum { MAT_NH = 1, MAT_SVK = 2 };
 constexpr int kNHState = 12;   // F^-T (9), a = s mu, b = s lam, c = s (mu - lam ln J)
-constexpr int kSVKState = 16;  // F (9), S in Voigt order 11 22 33 23 13 12 (6), s (1)
+constexpr int kSVKState = 10;  // H = F - I (9), s (1)
+constexpr int kStatePlanes = kNHState > kSVKState ? kNHState : kSVKState;
 
 // scalars shared by the CG kernels (device memory)
 struct CGScalars {
@@ -54,7 +55,7 @@ struct CGScalars {
   int status;      // 0 running, 1 converged, 2 breakdown, 3 iteration cap
 };
 
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -333,7 +334,12 @@ __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* 
 
 // Variant "rows": one thread transforms all three components of its columns in turn and
 // carries only the scalar s between the forward and the inverse transforms.
-template <typename T, int A, int B>
+// GHOM_XPF: prefetch of the next component in the "rows" x pass; -1 = float32 only (in
+// float64 the second register set would spill)
+#ifndef GHOM_XPF
+#define GHOM_XPF -1
+#endif
+template <typename T, int A, int B, bool XPF = (GHOM_XPF < 0 ? sizeof(T) == 4 : GHOM_XPF != 0)>
 __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
                                                 const cx<T>* __restrict__ tw, const ProjParams& pp,
                                                 const CGScalars* __restrict__ sc, int bx, int by) {
@@ -363,12 +369,24 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
   cx<T> a0[3];
 #pragma unroll
   for (int e = 0; e < B; ++e) s[e] = cx<T>{0, 0};
-#pragma nounroll
-  for (int l = 0; l < 3; ++l) {
+  auto load_comp = [&](int l, cx<T>* v) {
     const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + gcol;
-    cx<T> v[B];
 #pragma unroll
     for (int e = 0; e < B; ++e) v[e] = ok ? src[(long long)(q + A * e) * rs] : cx<T>{0, 0};
+  };
+  // XPF: the loads of the next component are in flight during this component's transform
+  cx<T> nxt[XPF ? B : 1];
+  if constexpr (XPF) load_comp(0, nxt);
+#pragma nounroll
+  for (int l = 0; l < 3; ++l) {
+    cx<T> v[B];
+    if constexpr (XPF) {
+#pragma unroll
+      for (int e = 0; e < B; ++e) v[e] = nxt[e];
+      if (l < 2) load_comp(l + 1, nxt);
+    } else {
+      load_comp(l, v);
+    }
     four_step_first<A, B, -1>(v, q, tw);
     if (l) __syncthreads();
 #pragma unroll
@@ -437,38 +455,51 @@ __device__ __forceinline__ void tangent_nh(const T* st, const T* d, T* out) {
 }
 
 // Saint Venant-Kirchhoff: K:dF = dF S + F (s C : sym(F^T dF)), C in 6x6 Voigt form
+// SVK tangent K : d = d S + F (C : sym(F^T d)) with F = I + H and S = s C : E(H),
+// E = (H + H^T + H^T H) / 2.  Only H and s are stored: S is rebuilt here from the grain's
+// stiffness, which the tangent needs anyway, and forming E from H (not F^T F - I) keeps
+// the small strains free of cancellation in the CG type.
 template <typename T>
-__device__ __forceinline__ void tangent_svk(const T* st, const T* __restrict__ C6, const T* d, T* out) {
-  const T* F = st;
-  const T* S = st + 9;  // 11 22 33 23 13 12
-  const T s = st[15];
-  T E[6];
-  // (F^T dF)_ij = sum_k F_ki dF_kj ; dE = sym
-  auto ftd = [&](int i, int jj) { return F[i] * d[jj] + F[3 + i] * d[3 + jj] + F[6 + i] * d[6 + jj]; };
-  E[0] = ftd(0, 0);
-  E[1] = ftd(1, 1);
-  E[2] = ftd(2, 2);
-  E[3] = ftd(1, 2) + ftd(2, 1);  // engineering shear 2 dE23
-  E[4] = ftd(0, 2) + ftd(2, 0);
-  E[5] = ftd(0, 1) + ftd(1, 0);
-  T dS[6];
+__device__ __forceinline__ void tangent_svk(const T* H, T s, const T* __restrict__ C6, const T* d, T* out) {
+  auto hth = [&](int i, int j) { return H[i] * H[j] + H[3 + i] * H[3 + j] + H[6 + i] * H[6 + j]; };
+  // (F^T d)_ij = d_ij + sum_k H_ki d_kj
+  auto ftd = [&](int i, int j) { return d[3 * i + j] + H[i] * d[j] + H[3 + i] * d[3 + j] + H[6 + i] * d[6 + j]; };
+  T E[6], dE[6];  // Voigt 11 22 33 23 13 12, engineering shears
+  E[0] = H[0] + (T)0.5 * hth(0, 0);
+  E[1] = H[4] + (T)0.5 * hth(1, 1);
+  E[2] = H[8] + (T)0.5 * hth(2, 2);
+  E[3] = H[5] + H[7] + hth(1, 2);
+  E[4] = H[2] + H[6] + hth(0, 2);
+  E[5] = H[1] + H[3] + hth(0, 1);
+  dE[0] = ftd(0, 0);
+  dE[1] = ftd(1, 1);
+  dE[2] = ftd(2, 2);
+  dE[3] = ftd(1, 2) + ftd(2, 1);
+  dE[4] = ftd(0, 2) + ftd(2, 0);
+  dE[5] = ftd(0, 1) + ftd(1, 0);
+  T S[6], dS[6];
 #pragma unroll
   for (int I = 0; I < 6; ++I) {
-    T acc = 0;
+    T a = 0, b = 0;
 #pragma unroll
-    for (int J = 0; J < 6; ++J) acc += C6[6 * I + J] * E[J];
-    dS[I] = s * acc;
+    for (int J = 0; J < 6; ++J) {
+      const T c = C6[6 * I + J];
+      a += c * E[J];
+      b += c * dE[J];
+    }
+    S[I] = s * a;
+    dS[I] = s * b;
   }
   const T Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
   const T dSm[9] = {dS[0], dS[5], dS[4], dS[5], dS[1], dS[3], dS[4], dS[3], dS[2]};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      T acc = 0;
+    for (int j = 0; j < 3; ++j) {
+      T acc = dSm[3 * i + j];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) acc += d[3 * i + k] * Sm[3 * k + jj] + F[3 * i + k] * dSm[3 * k + jj];
-      out[3 * i + jj] = acc;
+      for (int k = 0; k < 3; ++k) acc += d[3 * i + k] * Sm[3 * k + j] + H[3 * i + k] * dSm[3 * k + j];
+      out[3 * i + j] = acc;
     }
 }
 
@@ -486,7 +517,7 @@ struct ZfwdArgs {
   const T* state;             // tangent state planes
   const uint16_t* phase;      // SVK: phase of each voxel
   const T* C6;                // SVK: per-phase 6x6 Voigt stiffness in the CG type
-  int has_scale;              // SVK: state plane 15 holds s(x) (else s = 1)
+  int has_scale;              // SVK: state plane 9 holds s(x) (else s = 1)
   double* partials;           // nullable: per-block partial of sum p : (K : p) (FP64)
   cx<T>* H;                   // spectrum out
   const cx<T>* tw;            // z twiddles
@@ -533,11 +564,11 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
           for (int k = 0; k < kNHState; ++k) st[k] = args.state[k * g.N + vox];
           tangent_nh(st, d, val);
         } else {
-          T st[kSVKState];
+          T H[9];
 #pragma unroll
-          for (int k = 0; k < kSVKState - 1; ++k) st[k] = args.state[k * g.N + vox];
-          st[kSVKState - 1] = args.has_scale ? args.state[(kSVKState - 1) * g.N + vox] : (T)1;
-          tangent_svk(st, args.C6 + 36 * args.phase[vox], d, val);
+          for (int k = 0; k < 9; ++k) H[k] = args.state[k * g.N + vox];
+          const T sv = args.has_scale ? args.state[9 * g.N + vox] : (T)1;
+          tangent_svk(H, sv, args.C6 + 36 * args.phase[vox], d, val);
         }
         if (args.partials) {
 #pragma unroll
@@ -765,10 +796,8 @@ __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __
         for (int j = 0; j < 3; ++j)
           p[3 * i + j] = f[3 * i] * Sm[j] + f[3 * i + 1] * Sm[3 + j] + f[3 * i + 2] * Sm[6 + j];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)f[c];
-#pragma unroll
-      for (int I = 0; I < 6; ++I) state[(9 + I) * g.N + v] = (TS)S[I];
-      if (scale) state[15 * g.N + v] = (TS)s;
+      for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)(c % 4 == 0 ? f[c] - 1.0 : f[c]);
+      if (scale) state[9 * g.N + v] = (TS)s;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -806,12 +835,21 @@ __device__ __forceinline__ void cg_init_body(long long n, const double* __restri
   if (threadIdx.x == 0) partials[bx] = s;
 }
 
-// sum of nparts partials in a fixed order, by one block
+// sum of nparts partials in a fixed order, by one block; four independent loads in
+// flight per thread, so the block is not bound by one memory latency per partial
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ partials, int nparts, int stride,
                                                   int k, double* red) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kRedThreads) acc += partials[(long long)i * stride + k];
-  return block_sum<kRedThreads>(acc, red);
+  constexpr int NT = kRedThreads;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * NT < nparts; i += 4 * NT) {
+    a0 += partials[(long long)i * stride + k];
+    a1 += partials[(long long)(i + NT) * stride + k];
+    a2 += partials[(long long)(i + 2 * NT) * stride + k];
+    a3 += partials[(long long)(i + 3 * NT) * stride + k];
+  }
+  for (; i < nparts; i += NT) a0 += partials[(long long)i * stride + k];
+  return block_sum<NT>((a0 + a1) + (a2 + a3), red);
 }
 
 // which: 0 = start (rr from partials, converged test), 1 = alpha (pAp), 2 = beta (rr_new)
