@@ -206,10 +206,12 @@ class Solver:
     def set_control(self, mask):
         m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(9)
         self._check(lib().ghom_set_control(self._c, _ptr(m)))
+        self.mask = m.copy()
 
     def set_history(self, target):
         t = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 9)
         self._check(lib().ghom_set_history(self._c, t.shape[0], _ptr(t)))
+        self.nsteps = t.shape[0]
 
     def set_tolerances(self, newton_tol=1e-6, cg_tol=1e-8, cg_forcing=0.0, max_newton=50, max_cg=5000):
         self._check(lib().ghom_set_tolerances(self._c, newton_tol, cg_tol, cg_forcing, max_newton, max_cg))
@@ -412,3 +414,64 @@ class Batch:
         out = np.empty((9,) + self.shapes[i])
         self._check(lib().ghom_batch_get_field(self._b, int(i), int(which), _ptr(out)))
         return out
+
+
+def _autograd_function():
+    import torch
+
+    class HomogenizedResponse(torch.autograd.Function):
+        """Differentiable map s(x) -> (<F>, <P>) at the end of a solver's load history.
+
+        ``HomogenizedResponse.apply(s, solver)``: ``solver`` is a set-up Solver (material,
+        control, history, tolerances); s is the per-voxel stiffness scale (any torch tensor
+        of N values).  Forward sets s, restarts from F = I and runs every increment; it
+        returns <F> and <P> as float64 tensors of 9 values on the device of s.
+
+        Backward evaluates dJ/ds for J = g_F : <F> by the adjoint solve of the library
+        (ghom_adjoint_grad_scale with a = g_F) at the final state.  On stress-controlled
+        components <P> equals the prescribed value for every s, so its cotangent adds
+        nothing; a cotangent of <P> on a deformation-controlled component is rejected
+        (that derivative needs another adjoint right-hand side, which is not provided).
+        """
+
+        @staticmethod
+        def forward(ctx, s, solver):
+            sv = s.detach().to("cpu", torch.float64).reshape(-1).numpy()
+            if sv.size != solver.N:
+                raise ValueError("s must hold one value per voxel (%d), got %d" % (solver.N, sv.size))
+            solver.set_stiffness_scale(sv)
+            eye = np.broadcast_to(np.eye(3).reshape(9, 1, 1, 1), (9,) + solver.shape)
+            solver.load_state(eye, 0)
+            for _ in range(solver.nsteps):
+                solver.step()
+            Fbar, Pbar = solver.averages()
+            ctx.solver = solver
+            ctx.sv = sv.copy()
+            ctx.state = solver.save_state()
+            ctx.shape_s = s.shape
+            return (torch.as_tensor(Fbar, device=s.device), torch.as_tensor(Pbar, device=s.device))
+
+        @staticmethod
+        def backward(ctx, gF, gP):
+            solver = ctx.solver
+            if gP is not None:
+                gp = gP.detach().to("cpu", torch.float64).numpy()
+                fctl = np.asarray(solver.mask).reshape(9) == 0
+                if np.any(gp[fctl] != 0.0):
+                    raise NotImplementedError("gradient of <P> on deformation-controlled components")
+            a = np.zeros(9) if gF is None else gF.detach().to("cpu", torch.float64).numpy()
+            solver.set_stiffness_scale(ctx.sv)
+            solver.load_state(*ctx.state)
+            g = solver.adjoint_grad_scale(a)
+            dev = gF.device if gF is not None else gP.device
+            return torch.as_tensor(g, device=dev).reshape(ctx.shape_s), None
+
+    return HomogenizedResponse
+
+
+def __getattr__(name):
+    if name == "HomogenizedResponse":
+        fn = _autograd_function()
+        globals()[name] = fn
+        return fn
+    raise AttributeError(name)
