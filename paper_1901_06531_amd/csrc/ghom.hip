@@ -217,8 +217,8 @@ int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::str
   return grid;
 }
 
-template <typename T, typename TOUT, bool CGU>
-int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name) {
+template <typename T, typename TOUT, int ZM>
+int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name, int first = 0) {
   int grid = 0;
   with_split(c.nz, [&](auto s) {
     using S = decltype(s);
@@ -226,8 +226,8 @@ int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name) {
     const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
     timed(e, name, [&] {
-      hipLaunchKernelGGL((zinv_batch<T, S::A, S::B, TOUT, CGU>), dim3(grid, 1, (unsigned)c.probs.size()),
-                         dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role);
+      hipLaunchKernelGGL((zinv_batch<T, S::A, S::B, TOUT, ZM>), dim3(grid, 1, (unsigned)c.probs.size()),
+                         dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, first);
     });
   });
   return grid;
@@ -338,23 +338,27 @@ void tune_class(Engine& e, ShapeClass& c, int which) {
 }
 
 // out = scale * G*(in - Pbar) in float64 for every active problem of a class
-// role: ROLE_RESID (P -> b, with b.b partials), ROLE_REPROJ (x -> dF64), ROLE_PROJ (in -> out)
+// role: ROLE_RESID (P -> b, with b.b partials), ROLE_REPROJ (x -> dF64), ROLE_PROJ (in -> out),
+// ROLE_NEWTON (F += G*(x), Newton-update partials)
 int project64(Engine& e, ShapeClass& c, int role, const std::string& tag) {
   const std::string pre = tag + "_";
-  if (role == ROLE_REPROJ) launch_zfwd<double, Z_PLAIN, float>(e, c, role, 0, pre + "zfwd_f64");
+  const bool from_x = role == ROLE_REPROJ || role == ROLE_NEWTON;
+  if (from_x && e.prec == GHOM_FP32_SPLIT) launch_zfwd<double, Z_PLAIN, float>(e, c, role, 0, pre + "zfwd_f64");
   else launch_zfwd<double, Z_PLAIN, double>(e, c, role, 0, pre + "zfwd_f64");
   middle_passes<double>(e, c, role, pre);
-  return launch_zinv<double, double, false>(e, c, role, pre + "zinv_f64");
+  if (role == ROLE_NEWTON) return launch_zinv<double, double, ZI_NEWTON>(e, c, role, pre + "zinv_f64");
+  return launch_zinv<double, double, ZI_PLAIN>(e, c, role, pre + "zinv_f64");
 }
 
 // A(v) = G*(K : v) in the CG type.  ROLE_OP_CG: one CG step (see the kernels); returns the
 // z-pass grid (the partial count of its reductions).  ROLE_OP_PLAIN: in -> out.
+// update_p: 0 p as is, 1 p <- r + beta p, 2 CG start (r = p = b, x not read)
 template <typename T>
-int operator_apply(Engine& e, ShapeClass& c, int role, bool update_p) {
+int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
   const std::string t = tname<T>();
   int gz;
-  if (c.kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p ? 1 : 0, "op_zfwd_" + t);
-  else gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p ? 1 : 0, "op_zfwd_" + t);
+  if (c.kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p, "op_zfwd_" + t);
+  else gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
   if (role == ROLE_OP_CG) {
     timed(e, "cg_scalar", [&] {
       hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
@@ -362,8 +366,8 @@ int operator_apply(Engine& e, ShapeClass& c, int role, bool update_p) {
     });
   }
   middle_passes<T>(e, c, role, "op_");
-  if (role == ROLE_OP_CG) launch_zinv<T, T, true>(e, c, role, "op_zinv_" + t);
-  else launch_zinv<T, T, false>(e, c, role, "op_zinv_" + t);
+  if (role == ROLE_OP_CG) launch_zinv<T, T, ZI_CG>(e, c, role, "op_zinv_" + t, update_p == 2 ? 1 : 0);
+  else launch_zinv<T, T, ZI_PLAIN>(e, c, role, "op_zinv_" + t);
   return gz;
 }
 
@@ -391,7 +395,8 @@ void constitutive(Engine& e) {
       }
     });
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 18, 0);
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 18, 0, 0,
+                         0);
     });
   }
   const size_t n = e.P.size();
@@ -416,21 +421,57 @@ void constitutive(Engine& e) {
   }
 }
 
-// b = -G*(P - Pbar) in FP64 for every active problem; sets rms_b
-void residual(Engine& e) {
+// One Newton evaluation for every active problem: the constitutive update (P, tangent
+// state, <F>, <P>; det F <= 0 gives EDOMAIN) fused into the forward pass of the FP64
+// residual b = -G*(P - Pbar); sets rms_b and the r.r the next CG solve starts from.
+void constitutive_residual(Engine& e) {
+  constexpr int kRedB = 20;  // red[0..18): sums of F and P; red[20]: b.b
   for (auto& c : e.C) {
     if (!class_active(e, c)) continue;
-    const int grid = project64(e, c, ROLE_RESID, "res");
+    const int np = (int)c.probs.size();
+    hipLaunchKernelGGL(zero_flag_batch, dim3((np + 255) / 256), dim3(256), 0, e.stream, e.ddesc, c.ids, np);
+    HIPCALL(hipGetLastError());
+    int gz = 0;
+    if (c.kind == MAT_NH) {
+      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_NH, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+      else gz = launch_zfwd<double, Z_CONST_NH, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+    } else {
+      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_SVK, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+      else gz = launch_zfwd<double, Z_CONST_SVK, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+    }
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
-                         c.ids, grid, 1, 0);
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gz, 18, 0, 1, 0);
+    });
+    middle_passes<double>(e, c, ROLE_RESID, "res_");
+    const int gi = launch_zinv<double, double, ZI_PLAIN>(e, c, ROLE_RESID, "res_zinv_f64");
+    timed(e, "reduce", [&] {
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 1, 0, 0,
+                         kRedB);
     });
   }
   const size_t n = e.P.size();
   HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  HIPCALL(hipMemcpyAsync(e.host_flags, e.flags, n * sizeof(int), hipMemcpyDeviceToHost, e.stream));
   sync(e);
-  for (size_t p = 0; p < n; ++p)
-    if (e.hdesc[p].active) e.P[p].rms_b = std::sqrt(e.host_red[32 * p] / (double)e.C[e.P[p].cls].g.N);
+  for (size_t p = 0; p < n; ++p) {
+    if (!e.hdesc[p].active) continue;
+    Prob& q = e.P[p];
+    const double N = (double)e.C[q.cls].g.N;
+    for (int i = 0; i < 9; ++i) {
+      q.Favg[i] = e.host_red[32 * p + i] / N;
+      q.Pavg[i] = e.host_red[32 * p + 9 + i] / N;
+    }
+    q.state_valid = true;
+    const double bb = e.host_red[32 * p + kRedB];
+    q.rms_b = std::sqrt(bb / N);
+    e.hdesc[p].rr0 = bb;
+    if (e.host_flags[p]) {
+      q.state_valid = false;
+      q.status = GHOM_EDOMAIN;
+      q.msg = "det F <= 0 at some voxel";
+      q.running = false;
+    }
+  }
 }
 
 // Conjugate gradients on A dF = b from dF = 0 for every active problem; the stop test of
@@ -443,14 +484,8 @@ void cg_solve(Engine& e, double* t_ms) {
     const int np = (int)c.probs.size();
     for (int p : c.probs)
       if (e.hdesc[p].active) vox += c.g.N;
-    const int gi = vox_blocks(9 * c.g.N);
-    timed(e, "cg_init", [&] {
-      hipLaunchKernelGGL((cg_init_batch<T>), dim3(gi, 1, np), dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
-    });
-    if (!class_active(e, c)) continue;
-    timed(e, "cg_scalar", [&] {
-      hipLaunchKernelGGL(cg_scalar_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 0);
-    });
+    hipLaunchKernelGGL(cg_start_batch, dim3((np + 63) / 64), dim3(64), 0, e.stream, e.ddesc, c.ids, np);
+    HIPCALL(hipGetLastError());
   }
   // The host reads the device-side stop flags one chunk behind: while it waits for the
   // status copied after chunk k, chunk k+1 is already queued, so the GPU never idles on the
@@ -463,7 +498,7 @@ void cg_solve(Engine& e, double* t_ms) {
     for (int i = 0; i < k; ++i, ++enqueued) {
       for (auto& c : e.C) {
         if (!class_active(e, c)) continue;
-        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, enqueued > 0);
+        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, enqueued > 0 ? 1 : 2);
         timed(e, "cg_scalar", [&] {
           hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
                              c.ids, gz, 2);
@@ -495,19 +530,40 @@ void cg_solve(Engine& e, double* t_ms) {
   // that no copy into the slots is in flight when the caller reads slot 0
   HIPCALL(hipEventSynchronize(e.sc_ev[1 - slot]));
   if (slot != 0) std::copy(e.host_sc + n, e.host_sc + 2 * n, e.host_sc);
+  // the first iteration writes x; a problem that stopped before it gets x = 0
+  bool zeroed = false;
+  for (auto& c : e.C)
+    for (int p : c.probs)
+      if (e.hdesc[p].active && e.host_sc[p].it == 0 && e.host_sc[p].status == 1) {
+        const long long nd = (9LL * c.g.N * (long long)sizeof(T) + 7) / 8;  // arena buffers are padded
+        hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, nd, reinterpret_cast<double*>(e.hdesc[p].x));
+        HIPCALL(hipGetLastError());
+        zeroed = true;
+      }
+  if (zeroed) sync(e);
   if (t_ms) *t_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// F += dF for every active problem; sets crit = max |dF| / |<F>|
+// F += dF for every active problem; sets crit = max |dF| / |<F>|.  FP64: dF = x.
+// FP32-split: dF = G*(x) by one float64 transform pair, added to F by its last pass.
 void newton_update(Engine& e, std::vector<double>& crit) {
   for (auto& c : e.C) {
     if (!class_active(e, c)) continue;
     const int np = (int)c.probs.size();
+    if (e.prec == GHOM_FP32_SPLIT) {
+      const int gi = project64(e, c, ROLE_NEWTON, "reproj");
+      timed(e, "reduce", [&] {
+        hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 10, 1, 1,
+                           0);
+      });
+      continue;
+    }
     timed(e, "newton_update", [&] {
       hipLaunchKernelGGL(newton_update_batch, dim3(c.vb, 1, np), dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
     });
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 10, 1);
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 10, 1, 0,
+                         0);
     });
   }
   const size_t n = e.P.size();
@@ -564,10 +620,7 @@ void newton(Engine& e, const std::vector<int>& set) {
     set_active_from_running(e, set);
     for (int p : set)
       if (e.P[p].running) e.P[p].info.newton_iters += 1;
-    constitutive(e);
-    set_active_from_running(e, set);
-    if (!any_running(e, set)) break;
-    residual(e);
+    constitutive_residual(e);
     for (int p : set) {
       Prob& q = e.P[p];
       if (!q.running) continue;
@@ -612,9 +665,6 @@ void newton(Engine& e, const std::vector<int>& set) {
     }
     set_active_from_running(e, set);
     if (!any_running(e, set)) break;
-    if (e.prec == GHOM_FP32_SPLIT)
-      for (auto& c : e.C)
-        if (class_active(e, c)) project64(e, c, ROLE_REPROJ, "reproj");
     newton_update(e, crit);
     for (int p : set) {
       Prob& q = e.P[p];
@@ -631,9 +681,14 @@ void newton(Engine& e, const std::vector<int>& set) {
     }
   }
   for (int p : set) e.P[p].running = false;
-  // P and the averages at the final F of every problem of the solve (not after EDOMAIN)
+  // P and the averages at the final F of every problem of the solve (not after EDOMAIN;
+  // a problem whose last Newton evaluation was at its final F has them already)
   for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
-  for (int p : set) e.hdesc[p].active = e.P[p].status == GHOM_EDOMAIN ? 0 : 1;
+  bool need = false;
+  for (int p : set) {
+    e.hdesc[p].active = (e.P[p].status == GHOM_EDOMAIN || e.P[p].state_valid) ? 0 : 1;
+    need = need || e.hdesc[p].active;
+  }
   upload_descs(e);
   std::vector<int> keep_status(e.P.size());
   std::vector<std::string> keep_msg(e.P.size());
@@ -641,7 +696,7 @@ void newton(Engine& e, const std::vector<int>& set) {
     keep_status[p] = e.P[p].status;
     keep_msg[p] = e.P[p].msg;
   }
-  constitutive(e);
+  if (need) constitutive(e);
   for (int p : set)
     if (keep_status[p] != GHOM_EDOMAIN && e.P[p].state_valid) {
       e.P[p].status = keep_status[p];
@@ -797,9 +852,10 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   // partials per problem: the largest block count of any reducing launch
   size_t np = 64;
   for (auto& c : e.C) {
-    np = std::max(np, (size_t)c.nx * c.ny / 2 + 64);
+    // z passes: at most ceil(nx ny / 2) blocks, up to 18 partials each (fused residual
+    // pass); voxel kernels: c.vb blocks with up to 18 partials each
+    np = std::max(np, 18 * (((size_t)c.nx * c.ny + 1) / 2) + 64);
     np = std::max(np, (size_t)c.vb * 18);
-    np = std::max(np, (size_t)vox_blocks(9 * c.g.N));
   }
   e.np = np;
   // arena layout
@@ -1132,7 +1188,7 @@ int ghom_set_history(ghom_ctx* c, int nsteps, const double* target) {
 }
 
 static int set_tolerances(Engine& e, double newton_tol, double cg_tol, double cg_forcing, int max_newton, int max_cg) {
-  if (!(newton_tol > 0) || !(cg_tol > 0) || !(cg_forcing >= 0) || max_newton < 1 || max_cg < 1)
+  if (!(newton_tol > 0) || !(cg_tol > 0) || !(cg_forcing >= 0 && cg_forcing < 1) || max_newton < 1 || max_cg < 1)
     fail(GHOM_EINVAL, "bad tolerances");
   e.newton_tol = newton_tol;
   e.cg_tol = cg_tol;
@@ -1249,6 +1305,7 @@ int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
     e.hdesc[0].active = 1;
     const double tol = std::max(e.cg_tol, forcing(e) * std::sqrt(rr));
     e.hdesc[0].cg_thresh = tol * tol * (double)N;
+    e.hdesc[0].rr0 = rr * (double)N;
     e.hdesc[0].max_cg = e.max_cg;
     upload_descs(e);
     hipLaunchKernelGGL(fill9_batch, dim3(cl.vb, 1, 1), dim3(kVoxThreads), 0, e.stream, e.ddesc, cl.ids, 1);
@@ -1290,8 +1347,8 @@ int ghom_apply_operator(ghom_ctx* c, const void* v_dev, void* Av_dev) {
     e.hdesc[0].active = 1;
     upload_descs(e);
     ShapeClass& cl = e.C[e.P[0].cls];
-    if (e.prec == GHOM_FP64) operator_apply<double>(e, cl, ROLE_OP_PLAIN, false);
-    else operator_apply<float>(e, cl, ROLE_OP_PLAIN, false);
+    if (e.prec == GHOM_FP64) operator_apply<double>(e, cl, ROLE_OP_PLAIN, 0);
+    else operator_apply<float>(e, cl, ROLE_OP_PLAIN, 0);
     sync(e);
     e.hdesc[0].in = nullptr;
     e.hdesc[0].out = nullptr;

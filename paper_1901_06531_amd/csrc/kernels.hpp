@@ -98,6 +98,28 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return s;
 }
 
+// K block reductions at once, in the order of block_sum / block_max (so the results are
+// the same bits): columns k < NMAX take the max, the others the sum.  sh holds K * NW
+// doubles; thread k < K calls out(k, value).  Ends the block's use of sh (no barrier
+// after it).
+template <int NT, int K, int NMAX = 0, typename Out>
+__device__ __forceinline__ void block_reduce_cols(const double* v, double* sh, Out&& out) {
+  constexpr int NW = (NT + 63) / 64;
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = k < NMAX ? wave_max(v[k]) : wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) sh[k * NW + w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    const int k = threadIdx.x;
+    double s = 0.0;
+    for (int i = 0; i < NW; ++i) s = k < NMAX ? fmax(s, sh[k * NW + i]) : s + sh[k * NW + i];
+    out(k, s);
+  }
+}
+
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int pow2_floor(int v) {
@@ -503,25 +525,102 @@ __device__ __forceinline__ void tangent_svk(const T* H, T s, const T* __restrict
     }
 }
 
+// Constitutive update of one voxel in float64 (neo-Hookean or SVK, modulus scale s):
+// P(F) into p, the tangent state into planes of N values at voxel v (CG type TS).
+// Returns false when det F <= 0.
+template <typename TS, int KIND>
+__device__ __forceinline__ bool constitutive_point(const double* f, int ph, double s, bool has_scale,
+                                                   const double* __restrict__ mat, double* p, TS* __restrict__ state,
+                                                   long long N, long long v) {
+  const double cf0 = f[4] * f[8] - f[5] * f[7];
+  const double cf1 = f[5] * f[6] - f[3] * f[8];
+  const double cf2 = f[3] * f[7] - f[4] * f[6];
+  const double J = f[0] * cf0 + f[1] * cf1 + f[2] * cf2;
+  if constexpr (KIND == MAT_NH) {
+    const double mu = s * mat[2 * ph], lam = s * mat[2 * ph + 1];
+    // G = F^-T = cofactor(F) / J
+    const double iJ = 1.0 / J;
+    double G[9];
+    G[0] = cf0 * iJ;
+    G[1] = cf1 * iJ;
+    G[2] = cf2 * iJ;
+    G[3] = (f[2] * f[7] - f[1] * f[8]) * iJ;
+    G[4] = (f[0] * f[8] - f[2] * f[6]) * iJ;
+    G[5] = (f[1] * f[6] - f[0] * f[7]) * iJ;
+    G[6] = (f[1] * f[5] - f[2] * f[4]) * iJ;
+    G[7] = (f[2] * f[3] - f[0] * f[5]) * iJ;
+    G[8] = (f[0] * f[4] - f[1] * f[3]) * iJ;
+    const double lnJ = J > 0.0 ? log(J) : 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) p[c] = mu * (f[c] - G[c]) + lam * lnJ * G[c];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) state[c * N + v] = (TS)G[c];
+    state[9 * N + v] = (TS)mu;
+    state[10 * N + v] = (TS)lam;
+    state[11 * N + v] = (TS)(mu - lam * lnJ);
+  } else {
+    const double* C6 = mat + 36 * ph;
+    // E = (F^T F - I)/2 in Voigt with engineering shears
+    auto ftf = [&](int i, int j) { return f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j]; };
+    double E[6];
+    E[0] = 0.5 * (ftf(0, 0) - 1.0);
+    E[1] = 0.5 * (ftf(1, 1) - 1.0);
+    E[2] = 0.5 * (ftf(2, 2) - 1.0);
+    E[3] = ftf(1, 2);
+    E[4] = ftf(0, 2);
+    E[5] = ftf(0, 1);
+    double S[6];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      double acc = 0.0;
+#pragma unroll
+      for (int J2 = 0; J2 < 6; ++J2) acc += C6[6 * I + J2] * E[J2];
+      S[I] = s * acc;
+    }
+    const double Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        p[3 * i + j] = f[3 * i] * Sm[j] + f[3 * i + 1] * Sm[3 + j] + f[3 * i + 2] * Sm[6 + j];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) state[c * N + v] = (TS)(c % 4 == 0 ? f[c] - 1.0 : f[c]);
+    if (has_scale) state[9 * N + v] = (TS)s;
+  }
+  return J > 0.0;
+}
+
 // ---------------------------------------------------------------------------------
 // z forward pass: per voxel input (plain copy or K : p), real-to-complex along z
 // ---------------------------------------------------------------------------------
-enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2 };
+// Z_CONST_*: the forward pass of the Newton residual with the constitutive update fused
+// in: F -> P (written), tangent state (written, CG type TIN), sums of F and P per block,
+// and P goes into the transform.
+enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2, Z_CONST_NH = 3, Z_CONST_SVK = 4 };
 
 template <typename T, typename TIN>
 struct ZfwdArgs {
   const TIN* in;              // Z_PLAIN: field to transform (9 planes)
   T* p;                       // Z_NH/Z_SVK: CG direction (updated in place when update_p)
-  const T* r;                 // CG residual for p <- r + beta p
-  int update_p;               // nonzero: p <- r + beta p before use
+  T* r;                       // CG residual
+  const double* b;            // update_p == 2: the Newton right-hand side
+  int update_p;               // 0: p as is; 1: p <- r + beta p; 2 (CG start): r <- b, p <- b
   const T* state;             // tangent state planes
   const uint16_t* phase;      // SVK: phase of each voxel
   const T* C6;                // SVK: per-phase 6x6 Voigt stiffness in the CG type
   int has_scale;              // SVK: state plane 9 holds s(x) (else s = 1)
-  double* partials;           // nullable: per-block partial of sum p : (K : p) (FP64)
+  double* partials;           // nullable: per-block partials (p : K : p, or the Z_CONST sums)
   cx<T>* H;                   // spectrum out
   const cx<T>* tw;            // z twiddles
   const CGScalars* sc;        // early exit / beta (nullable)
+  // Z_CONST_*
+  const double* F;            // deformation gradient
+  double* P;                  // stress out
+  TIN* state_out;             // tangent state out
+  const double* scale;        // per-voxel modulus scale (nullable)
+  const double* mat;          // per-phase material table (float64)
+  int* flag;                  // set when det F <= 0 somewhere
+  int pstride;                // Z_CONST sums: column k of block bx at partials[k * pstride + bx]
 };
 
 template <typename T, int A, int B, int MODE, typename TIN>
@@ -530,12 +629,18 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
+  constexpr bool CONST = MODE == Z_CONST_NH || MODE == Z_CONST_SVK;
+  constexpr bool CG = MODE == Z_NH || MODE == Z_SVK;
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
   const long long line0 = (long long)bx * (2 * LP);
   T* ldsr = reinterpret_cast<T*>(lds);
   double pkp = 0.0;
-  const T beta = (MODE != Z_PLAIN && args.update_p) ? (T)args.sc->beta : (T)0;
+  double cs[CONST ? 18 : 1];  // Z_CONST: sums of F and P
+#pragma unroll
+  for (int k = 0; k < (CONST ? 18 : 1); ++k) cs[k] = 0.0;
+  int bad = 0;
+  const T beta = (CG && args.update_p == 1) ? (T)args.sc->beta : (T)0;
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
@@ -546,16 +651,41 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
       if constexpr (MODE == Z_PLAIN) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) val[c] = (T)args.in[c * g.N + vox];
+      } else if constexpr (CONST) {
+        double f[9], pv[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) f[c] = args.F[c * g.N + vox];
+        const double sv = args.scale ? args.scale[vox] : 1.0;
+        if (!constitutive_point<TIN, MODE == Z_CONST_NH ? MAT_NH : MAT_SVK>(f, args.phase[vox], sv, args.scale != nullptr,
+                                                                            args.mat, pv, args.state_out, g.N, vox))
+          bad = 1;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          args.P[c * g.N + vox] = pv[c];
+          val[c] = (T)pv[c];
+          cs[c] += f[c];
+          cs[9 + c] += pv[c];
+        }
       } else {
         T d[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) d[c] = args.p[c * g.N + vox];
-        if (args.update_p) {
+        if (args.update_p == 2) {
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const long long i = c * g.N + vox;
-            d[c] = args.r[i] + beta * d[c];
+            d[c] = (T)args.b[i];
+            args.r[i] = d[c];
             args.p[i] = d[c];
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) d[c] = args.p[c * g.N + vox];
+          if (args.update_p == 1) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+              const long long i = c * g.N + vox;
+              d[c] = args.r[i] + beta * d[c];
+              args.p[i] = d[c];
+            }
           }
         }
         if constexpr (MODE == Z_NH) {
@@ -621,7 +751,11 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
     if (l0 < nlines) args.H[c * g.Nh + l0 * nzh + kz] = Ak;
     if (l0 + 1 < nlines) args.H[c * g.Nh + (l0 + 1) * nzh + kz] = Bk;
   }
-  if (args.partials) {
+  if constexpr (CONST) {
+    if (bad) atomicOr(args.flag, 1);
+    __shared__ double sh[18 * ((NT + 63) / 64)];
+    block_reduce_cols<NT, 18>(cs, sh, [&](int k, double t) { args.partials[(long long)k * args.pstride + bx] = t; });
+  } else if (args.partials) {
     const double t = block_sum<NT>(pkp, red);
     if (threadIdx.x == 0) args.partials[bx] = t;
   }
@@ -630,20 +764,28 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
 // ---------------------------------------------------------------------------------
 // z inverse pass: complex-to-real along z, write the field, fused partial dot products
 // ---------------------------------------------------------------------------------
+// ZI_PLAIN: the field goes to `out`; ZI_CG: CG update x += alpha p (x = alpha p on the
+// first iteration), r -= alpha A p, partial r.r; ZI_NEWTON: Newton update F += field with
+// the partials of max_x |dF(x)|^2 and of the sums of the new F (float64)
+enum { ZI_PLAIN = 0, ZI_CG = 1, ZI_NEWTON = 2 };
+
 template <typename T, typename TOUT>
 struct ZinvArgs {
   const cx<T>* H;
-  TOUT* out;                  // 9 planes (plain mode)
-  TOUT* x;                    // CG mode: x += alpha p, r -= alpha A p, partial r.r
+  TOUT* out;                  // ZI_PLAIN: 9 planes
+  TOUT* x;                    // ZI_CG
   TOUT* r;
   const TOUT* p;
-  const TOUT* dot_with;       // nullable: partial sum of out . dot_with per block
-  double* partials;           // one value per block when dot_with != nullptr
+  int first;                  // ZI_CG: first iteration (x is not read)
+  double* F;                  // ZI_NEWTON
+  const TOUT* dot_with;       // ZI_PLAIN, nullable: partial sum of out . dot_with per block
+  double* partials;           // ZI_CG / dot_with: one per block; ZI_NEWTON: 10 columns
+  int pstride;                // ZI_NEWTON: column k of block bx at partials[k * pstride + bx]
   const cx<T>* tw;
   const CGScalars* sc;        // early exit (nullable)
 };
 
-template <typename T, int A, int B, typename TOUT, bool CGU>
+template <typename T, int A, int B, typename TOUT, int ZM>
 __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>& args, int bx) {
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
@@ -691,30 +833,47 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
   // phase 3: real lines out
   const T* ldsr = reinterpret_cast<const T*>(lds);
   double acc = 0.0;
-  const TOUT alpha = CGU ? (TOUT)args.sc->alpha : (TOUT)0;
+  double fs[ZM == ZI_NEWTON ? 9 : 1];
+#pragma unroll
+  for (int c = 0; c < (ZM == ZI_NEWTON ? 9 : 1); ++c) fs[c] = 0.0;
+  const TOUT alpha = ZM == ZI_CG ? (TOUT)args.sc->alpha : (TOUT)0;
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
     const long long line = line0 + lp;
     if (line >= nlines) continue;
     const long long vox = line * NZ + z;
     const int pair = lp >> 1, part = lp & 1;
+    double n2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
       const long long i = c * g.N + vox;
-      if constexpr (CGU) {
-        const TOUT xv = args.x[i] + alpha * args.p[i];
+      if constexpr (ZM == ZI_CG) {
+        const TOUT xv = (args.first ? (TOUT)0 : args.x[i]) + alpha * args.p[i];
         const TOUT rv = args.r[i] - alpha * o;
         args.x[i] = xv;
         args.r[i] = rv;
         acc += (double)rv * (double)rv;
+      } else if constexpr (ZM == ZI_NEWTON) {
+        const double fn = args.F[i] + (double)o;
+        args.F[i] = fn;
+        n2 += (double)o * (double)o;
+        fs[c] += fn;
       } else {
         args.out[i] = o;
         if (args.dot_with) acc += (double)o * (double)args.dot_with[i];
       }
     }
+    if constexpr (ZM == ZI_NEWTON) acc = fmax(acc, n2);
   }
-  if (CGU || args.dot_with) {
+  if constexpr (ZM == ZI_NEWTON) {
+    __shared__ double sh[10 * ((NT + 63) / 64)];
+    double v[10];
+    v[0] = acc;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[1 + c] = fs[c];
+    block_reduce_cols<NT, 10, 1>(v, sh, [&](int k, double t) { args.partials[(long long)k * args.pstride + bx] = t; });
+  } else if (ZM == ZI_CG || args.dot_with) {
     const double s = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) args.partials[bx] = s;
   }
@@ -731,7 +890,6 @@ __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __
                                                   const double* __restrict__ scale, const double* __restrict__ mat,
                                                   double* __restrict__ partials, int* __restrict__ flag, int bx,
                                                   int gx) {
-  __shared__ double red[kVoxThreads / 64];
   double sums[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) sums[k] = 0.0;
@@ -741,64 +899,8 @@ __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __
     double f[9], p[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) f[c] = F[c * g.N + v];
-    const int ph = phase[v];
-    const double s = scale ? scale[v] : 1.0;
-    const double cf0 = f[4] * f[8] - f[5] * f[7];
-    const double cf1 = f[5] * f[6] - f[3] * f[8];
-    const double cf2 = f[3] * f[7] - f[4] * f[6];
-    const double J = f[0] * cf0 + f[1] * cf1 + f[2] * cf2;
-    if (!(J > 0.0)) bad = 1;
-    if constexpr (KIND == MAT_NH) {
-      const double mu = s * mat[2 * ph], lam = s * mat[2 * ph + 1];
-      // G = F^-T = cofactor(F) / J
-      const double iJ = 1.0 / J;
-      double G[9];
-      G[0] = cf0 * iJ;
-      G[1] = cf1 * iJ;
-      G[2] = cf2 * iJ;
-      G[3] = (f[2] * f[7] - f[1] * f[8]) * iJ;
-      G[4] = (f[0] * f[8] - f[2] * f[6]) * iJ;
-      G[5] = (f[1] * f[6] - f[0] * f[7]) * iJ;
-      G[6] = (f[1] * f[5] - f[2] * f[4]) * iJ;
-      G[7] = (f[2] * f[3] - f[0] * f[5]) * iJ;
-      G[8] = (f[0] * f[4] - f[1] * f[3]) * iJ;
-      const double lnJ = J > 0.0 ? log(J) : 0.0;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) p[c] = mu * (f[c] - G[c]) + lam * lnJ * G[c];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)G[c];
-      state[9 * g.N + v] = (TS)mu;
-      state[10 * g.N + v] = (TS)lam;
-      state[11 * g.N + v] = (TS)(mu - lam * lnJ);
-    } else {
-      const double* C6 = mat + 36 * ph;
-      // E = (F^T F - I)/2 in Voigt with engineering shears
-      auto ftf = [&](int i, int j) { return f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j]; };
-      double E[6];
-      E[0] = 0.5 * (ftf(0, 0) - 1.0);
-      E[1] = 0.5 * (ftf(1, 1) - 1.0);
-      E[2] = 0.5 * (ftf(2, 2) - 1.0);
-      E[3] = ftf(1, 2);
-      E[4] = ftf(0, 2);
-      E[5] = ftf(0, 1);
-      double S[6];
-#pragma unroll
-      for (int I = 0; I < 6; ++I) {
-        double acc = 0.0;
-#pragma unroll
-        for (int J2 = 0; J2 < 6; ++J2) acc += C6[6 * I + J2] * E[J2];
-        S[I] = s * acc;
-      }
-      const double Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          p[3 * i + j] = f[3 * i] * Sm[j] + f[3 * i + 1] * Sm[3 + j] + f[3 * i + 2] * Sm[6 + j];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) state[c * g.N + v] = (TS)(c % 4 == 0 ? f[c] - 1.0 : f[c]);
-      if (scale) state[9 * g.N + v] = (TS)s;
-    }
+    if (!constitutive_point<TS, KIND>(f, phase[v], scale ? scale[v] : 1.0, scale != nullptr, mat, p, state, g.N, v))
+      bad = 1;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       P[c * g.N + v] = p[c];
@@ -807,68 +909,39 @@ __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __
     }
   }
   if (bad) atomicOr(flag, 1);
-#pragma unroll
-  for (int k = 0; k < 18; ++k) {
-    const double s = block_sum<kVoxThreads>(sums[k], red);
-    if (threadIdx.x == 0) partials[(long long)bx * 18 + k] = s;
-  }
+  __shared__ double sh[18 * (kVoxThreads / 64)];
+  block_reduce_cols<kVoxThreads, 18>(sums, sh, [&](int k, double t) { partials[(long long)bx * 18 + k] = t; });
 }
 
 // ---------------------------------------------------------------------------------
 // CG vector kernels
 // ---------------------------------------------------------------------------------
-// x = 0, r = (T) b, p = r, partial r.r
-template <typename T>
-__device__ __forceinline__ void cg_init_body(long long n, const double* __restrict__ b, T* __restrict__ x,
-                                             T* __restrict__ r, T* __restrict__ p, double* __restrict__ partials,
-                                             int bx, int gx) {
-  __shared__ double red[kVoxThreads / 64];
-  double acc = 0.0;
-  for (long long i = (long long)bx * kVoxThreads + threadIdx.x; i < n; i += (long long)gx * kVoxThreads) {
-    const T v = (T)b[i];
-    x[i] = (T)0;
-    r[i] = v;
-    p[i] = v;
-    acc += (double)v * (double)v;
-  }
-  const double s = block_sum<kVoxThreads>(acc, red);
-  if (threadIdx.x == 0) partials[bx] = s;
-}
 
 // sum of nparts partials in a fixed order, by one block; four independent loads in
 // flight per thread, so the block is not bound by one memory latency per partial
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ partials, int nparts, int stride,
-                                                  int k, double* red) {
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ base, int nparts, long long stride,
+                                                  double* red) {
   constexpr int NT = kRedThreads;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int i = threadIdx.x;
   for (; i + 3 * NT < nparts; i += 4 * NT) {
-    a0 += partials[(long long)i * stride + k];
-    a1 += partials[(long long)(i + NT) * stride + k];
-    a2 += partials[(long long)(i + 2 * NT) * stride + k];
-    a3 += partials[(long long)(i + 3 * NT) * stride + k];
+    a0 += base[(long long)i * stride];
+    a1 += base[(long long)(i + NT) * stride];
+    a2 += base[(long long)(i + 2 * NT) * stride];
+    a3 += base[(long long)(i + 3 * NT) * stride];
   }
-  for (; i < nparts; i += NT) a0 += partials[(long long)i * stride + k];
+  for (; i < nparts; i += NT) a0 += base[(long long)i * stride];
   return block_sum<NT>((a0 + a1) + (a2 + a3), red);
 }
 
-// which: 0 = start (rr from partials, converged test), 1 = alpha (pAp), 2 = beta (rr_new)
+// which: 1 = alpha (from p.Ap), 2 = beta (from the new r.r)
 __device__ __forceinline__ void cg_scalar_body(CGScalars* sc, const double* __restrict__ partials, int nparts,
                                                int which) {
   __shared__ double red[kRedThreads / 64];
-  if (which != 0 && sc->done) return;
-  const double s = reduce_partials(partials, nparts, 1, 0, red);
+  if (sc->done) return;
+  const double s = reduce_partials(partials, nparts, 1, red);
   if (threadIdx.x != 0) return;
-  if (which == 0) {
-    sc->rr = s;
-    sc->it = 0;
-    sc->done = 0;
-    sc->status = 0;
-    if (s <= sc->thresh) {
-      sc->done = 1;
-      sc->status = 1;
-    }
-  } else if (which == 1) {
+  if (which == 1) {
     sc->pAp = s;
     if (!(s > 0.0) || !isfinite(s)) {
       sc->done = 1;
@@ -890,19 +963,21 @@ __device__ __forceinline__ void cg_scalar_body(CGScalars* sc, const double* __re
   }
 }
 
-// column sums of a (nparts x K) partials table into out[0..K); the first nmax columns
-// are reduced with max instead of sum (one block, fixed order)
+// column sums of a partials table (entry (i, k) at partials[i * si + k * sk], i < nparts,
+// k < K) into out[0..K); the first nmax columns are reduced with max instead of sum (one
+// block, fixed order)
 __device__ __forceinline__ void sum_columns_body(const double* __restrict__ partials, int nparts, int K, int nmax,
-                                                 double* __restrict__ out) {
+                                                 long long si, long long sk, double* __restrict__ out) {
   __shared__ double red[kRedThreads / 64];
   for (int k = 0; k < K; ++k) {
     double r;
+    const double* base = partials + (long long)k * sk;
     if (k < nmax) {
       double acc = 0.0;
-      for (int i = threadIdx.x; i < nparts; i += kRedThreads) acc = fmax(acc, partials[(long long)i * K + k]);
+      for (int i = threadIdx.x; i < nparts; i += kRedThreads) acc = fmax(acc, base[(long long)i * si]);
       r = block_max<kRedThreads>(acc, red);
     } else {
-      r = reduce_partials(partials, nparts, K, k, red);
+      r = reduce_partials(base, nparts, si, red);
     }
     if (threadIdx.x == 0) out[k] = r;
   }
@@ -912,7 +987,7 @@ __device__ __forceinline__ void sum_columns_body(const double* __restrict__ part
 template <typename TD>
 __device__ __forceinline__ void newton_update_body(const Geo& g, double* __restrict__ F, const TD* __restrict__ dF,
                                                    double* __restrict__ partials, int bx, int gx) {
-  __shared__ double red[kVoxThreads / 64];
+  __shared__ double red[10 * (kVoxThreads / 64)];
   double mx = 0.0;
   double sums[9];
 #pragma unroll
@@ -929,13 +1004,11 @@ __device__ __forceinline__ void newton_update_body(const Geo& g, double* __restr
     }
     mx = fmax(mx, n2);
   }
-  const double m = block_max<kVoxThreads>(mx, red);
-  if (threadIdx.x == 0) partials[(long long)bx * 10] = m;
+  double v[10];
+  v[0] = mx;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    const double s = block_sum<kVoxThreads>(sums[c], red);
-    if (threadIdx.x == 0) partials[(long long)bx * 10 + 1 + c] = s;
-  }
+  for (int c = 0; c < 9; ++c) v[1 + c] = sums[c];
+  block_reduce_cols<kVoxThreads, 10, 1>(v, red, [&](int k, double t) { partials[(long long)bx * 10 + k] = t; });
 }
 
 __device__ __forceinline__ void shift_body(long long N, double* __restrict__ F, const double* s, int bx, int gx) {
@@ -977,7 +1050,8 @@ enum {
   ROLE_OP_PLAIN = 1,  // operator on `in`, result to `out`
   ROLE_RESID = 2,     // -G*(P - P-bar) into b, with b.b partials
   ROLE_REPROJ = 3,    // G*(x) into dF64 (float64)
-  ROLE_PROJ = 4       // G*(in) into out (float64)
+  ROLE_PROJ = 4,      // G*(in) into out (float64)
+  ROLE_NEWTON = 5     // F += G*(x) (float64) with the Newton-update partials
 };
 
 struct ProbDesc {
@@ -990,6 +1064,7 @@ struct ProbDesc {
   double shift[9];   // uniform shift of the deformation-controlled means
   double fill[9];    // value of a uniform fill
   double cg_thresh;  // CG stop: r.r <= cg_thresh
+  double rr0;        // b.b of the right-hand side the next CG solve starts from
   int max_cg;
   double *F, *P, *b, *dF64;
   void *x, *r, *p, *state, *H;
@@ -1026,14 +1101,25 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   ZfwdArgs<T, TIN> a{};
-  if constexpr (MODE == Z_PLAIN) {
+  if constexpr (MODE == Z_CONST_NH || MODE == Z_CONST_SVK) {
+    a.F = d.F;
+    a.P = d.P;
+    a.state_out = reinterpret_cast<TIN*>(d.state);
+    a.phase = d.phase;
+    a.scale = d.has_scale ? d.scale : nullptr;
+    a.mat = d.mat;
+    a.flag = d.flag;
+    a.partials = d.partials;
+    a.pstride = (int)gridDim.x;
+  } else if constexpr (MODE == Z_PLAIN) {
     a.in = role == ROLE_RESID ? reinterpret_cast<const TIN*>(d.P)
-                              : (role == ROLE_REPROJ ? reinterpret_cast<const TIN*>(d.x)
+                              : ((role == ROLE_REPROJ || role == ROLE_NEWTON) ? reinterpret_cast<const TIN*>(d.x)
                                                      : reinterpret_cast<const TIN*>(d.in));
   } else {
     const bool cg = role == ROLE_OP_CG;
     a.p = cg ? reinterpret_cast<T*>(d.p) : const_cast<T*>(reinterpret_cast<const T*>(d.in));
-    a.r = reinterpret_cast<const T*>(d.r);
+    a.r = reinterpret_cast<T*>(d.r);
+    a.b = d.b;
     a.update_p = cg ? update_p : 0;
     a.state = reinterpret_cast<const T*>(d.state);
     a.phase = d.phase;
@@ -1077,26 +1163,30 @@ xproj_groups_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, 
                              role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int A, int B, typename TOUT, bool CGU>
+template <typename T, int A, int B, typename TOUT, int ZM>
 __global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
-zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role) {
+zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, int first) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   ZinvArgs<T, TOUT> a{};
   a.H = reinterpret_cast<const cx<T>*>(d.H);
   a.tw = twd<T>(d, 2);
   a.partials = d.partials;
-  if constexpr (CGU) {
+  if constexpr (ZM == ZI_CG) {
     a.x = reinterpret_cast<TOUT*>(d.x);
     a.r = reinterpret_cast<TOUT*>(d.r);
     a.p = reinterpret_cast<const TOUT*>(d.p);
     a.sc = d.sc;
+    a.first = first;
+  } else if constexpr (ZM == ZI_NEWTON) {
+    a.F = d.F;
+    a.pstride = (int)gridDim.x;
   } else {
     a.out = role == ROLE_RESID ? reinterpret_cast<TOUT*>(d.b)
                                : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
     a.dot_with = role == ROLE_RESID ? a.out : nullptr;
   }
-  zinv_body<T, A, B, TOUT, CGU>(d.g, a, blockIdx.x);
+  zinv_body<T, A, B, TOUT, ZM>(d.g, a, blockIdx.x);
 }
 
 template <typename TS, int KIND>
@@ -1108,22 +1198,22 @@ constitutive_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) 
                               d.mat, d.partials, d.flag, blockIdx.x, gridDim.x);
 }
 
-// r = (T) b, x = 0, p = r with r.r partials; the CG scalars are reset for every problem
-// (inactive ones start finished)
-template <typename T>
-__global__ void __launch_bounds__(kVoxThreads)
-cg_init_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
-  const ProbDesc& d = D[ids[blockIdx.z]];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    d.sc->thresh = d.cg_thresh;
-    d.sc->max_it = d.max_cg;
-    d.sc->it = 0;
-    d.sc->done = d.active ? 0 : 1;
-    d.sc->status = d.active ? 0 : 1;
-  }
-  if (!d.active) return;
-  cg_init_body<T>(9 * d.g.N, d.b, reinterpret_cast<T*>(d.x), reinterpret_cast<T*>(d.r), reinterpret_cast<T*>(d.p),
-                  d.partials, blockIdx.x, gridDim.x);
+
+// CG start for every problem of a launch (one thread each): stop rule, iteration cap and
+// r.r = b.b from the descriptor.  The first iteration's passes take r = p = b and x = 0
+// themselves.  A problem that needs no iteration (or takes no part) starts finished.
+__global__ void cg_start_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int np) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const ProbDesc& d = D[ids[i]];
+  CGScalars* sc = d.sc;
+  sc->thresh = d.cg_thresh;
+  sc->max_it = d.max_cg;
+  sc->it = 0;
+  sc->rr = d.rr0;
+  const int stop = !d.active || !(d.rr0 > d.cg_thresh);
+  sc->done = stop;
+  sc->status = stop ? 1 : 0;
 }
 
 // one block per problem
@@ -1134,11 +1224,14 @@ cg_scalar_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int
   cg_scalar_body(d.sc, d.partials, nparts, which);
 }
 
+// layout 0: entry (i, k) at i * K + k; layout 1: at k * nparts + i.  Results go to
+// red[off .. off + K).
 __global__ void __launch_bounds__(kRedThreads)
-sum_columns_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int K, int nmax) {
+sum_columns_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int K, int nmax,
+                  int layout, int off) {
   const ProbDesc& d = D[ids[blockIdx.x]];
   if (!d.active) return;
-  sum_columns_body(d.partials, nparts, K, nmax, d.red);
+  sum_columns_body(d.partials, nparts, K, nmax, layout ? 1 : K, layout ? nparts : 1, d.red + off);
 }
 
 // F += dF with dF the float64 correction: x itself in FP64 mode, the re-projected dF64 in
