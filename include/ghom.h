@@ -114,7 +114,8 @@ int ghom_set_history(ghom_ctx *ctx, int nsteps, const double *target);
 /* Stopping rules (Sec. 4): CG stops when the voxel-averaged L2 norm of its residual,
  * sqrt(sum |r|^2 / N), is <= max(cg_tol, cg_forcing * that norm of the right-hand side);
  * Newton stops when max_x |dF(x)| / |<F>| < newton_tol, or when the residual itself is
- * already <= cg_tol.  Defaults: 1e-6, 1e-8, 0, 50, 5000. */
+ * already <= cg_tol.  Defaults: 1e-6, 1e-8, 0, 50, 5000.  GHOM_EINVAL unless
+ * newton_tol > 0, cg_tol > 0, 0 <= cg_forcing < 1, max_newton >= 1 and max_cg >= 1. */
 int ghom_set_tolerances(ghom_ctx *ctx, double newton_tol, double cg_tol, double cg_forcing,
                         int max_newton, int max_cg);
 
