@@ -208,6 +208,68 @@ def cpu_baseline(w, max_seconds=30.0):
                       "(%.1f s)" % (its, w["name"], dt)}
 
 
+def run_paper_example(n, nsteps, precision_name):
+    """The three control types of the particle example (Sec. 3.1) on one geometry: (1)
+    mixed (F11 ramp, transverse stresses zero), (2) full stress control ramping to case
+    (1)'s end stress, (3) full strain control ramping to case (1)'s end deformation
+    gradient.  Per increment: Newton and CG iterations and time (the paper's Fig. 3a and
+    3c); at the end: how far the three end states are apart (rotation invariants)."""
+    from paper_1901_06531_amd import ghom, synth
+
+    prec = ghom.FP64 if precision_name == "fp64" else ghom.FP32_SPLIT
+    w1 = synth.workload_paper_particles(n=n, nsteps=nsteps)
+
+    def run(w):
+        with ghom.Solver(w["shape"], precision=prec) as s:
+            s.setup(w)
+            s.set_tolerances(w["newton_tol"], w["cg_tol"], CG_FORCING if prec == ghom.FP32_SPLIT else 0.0)
+            recs = []
+            for k in range(len(w["target"])):
+                info = s.step()
+                F, P = s.averages()
+                recs.append((info, F, P))
+            Ff = s.field(ghom.FIELD_F)
+        return recs, Ff
+
+    cases = {}
+    log("case (1): mixed control")
+    r1, F1 = run(w1)
+    F_end, P_end = r1[-1][1], r1[-1][2]
+    w2 = dict(w1, mask=synth.mask_full_stress(), target=synth.history_stress_ramp(P_end, nsteps))
+    log("case (2): full stress control")
+    r2, F2 = run(w2)
+    w3 = dict(w1, mask=synth.mask_full_strain(), target=synth.history_strain_ramp(F_end, nsteps))
+    log("case (3): full strain control")
+    r3, F3 = run(w3)
+
+    def cbar(F9):
+        F = np.asarray(F9).reshape(3, 3)
+        return F.T @ F
+
+    def ftf(Ff):
+        G = Ff.reshape(3, 3, -1)
+        return np.einsum("kin,kjn->ijn", G, G)
+
+    C1 = ftf(F1)
+    for name, recs, Ff in (("1_mixed", r1, F1), ("2_stress", r2, F2), ("3_strain", r3, F3)):
+        cases[name] = {
+            "cg_per_increment": [r[0]["cg_iters_total"] for r in recs],
+            "newton_per_increment": [r[0]["newton_iters"] for r in recs],
+            "ms_per_increment": [round(r[0]["t_total_ms"], 2) for r in recs],
+            "total_cg": int(sum(r[0]["cg_iters_total"] for r in recs)),
+            "total_ms": round(sum(r[0]["t_total_ms"] for r in recs), 1),
+            "P_mid": [round(v, 8) for v in recs[len(recs) // 2 - 1][2]],
+            "end_P_diff_vs_1": float(np.max(np.abs(recs[-1][2] - P_end))),
+            "end_Cbar_diff_vs_1": float(np.max(np.abs(cbar(recs[-1][1]) - cbar(F_end)))),
+            "end_voxel_FtF_diff_vs_1": float(np.max(np.abs(ftf(Ff) - C1))),
+        }
+    t3 = cases["3_strain"]["total_ms"]
+    for c in cases.values():
+        c["time_vs_case3"] = round(c["total_ms"] / t3, 3)
+    return {"paper_example": {"grid": [n, n, n], "increments": nsteps, "precision": precision_name,
+                              "newton_tol": w1["newton_tol"], "cg_tol": w1["cg_tol"], "cases": cases}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,12 +279,20 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 384-problem workload")
+    ap.add_argument("--paper-example", action="store_true",
+                    help="only run the three control types of the particle example (Sec. 3.1) and print their "
+                         "iteration counts, times and end-state differences")
+    ap.add_argument("--paper-example-precision", default="fp64", choices=["fp64", "split"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (5 times): the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.paper_example:
+        print(json.dumps(run_paper_example(64, 100, args.paper_example_precision)), flush=True)
+        return
 
     if args.copy_calibration:
         import torch

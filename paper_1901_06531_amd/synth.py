@@ -301,6 +301,33 @@ def workload_adjoint(n=128, seed_geo=1, seed_s=5, nsteps=10):
     return base
 
 
+def workload_paper_particles(n=64, nsteps=100):
+    """The particle-reinforced example of Sec. 3.1 with a synthetic geometry: 4 equal spheres
+    at volume fraction 0.2 on the sites of a face-centred cubic cell shifted by (1/4, 1/4,
+    1/4), an isotropic SVK matrix with shear modulus 28 and bulk modulus 46.67 (so
+    lambda = 28) and particles ten times stiffer in both moduli.  The case-(1) control: F11
+    ramps to 1.2 over ``nsteps`` increments, F12 = F13 = F23 = 0 prescribed, every other
+    stress component zero.  Cases (2) and (3) are built from case (1)'s end state
+    (history_stress_ramp, history_strain_ramp).
+
+    The voxelized cell is symmetric under the reflections x -> 1/2 - x (and likewise in y, z)
+    for even n, so case (1) ends with a diagonal stress: a stress target with a skew part
+    cannot be reached from F = I, where the tangent annihilates uniform rotations."""
+    a, b = 0.25, 0.75
+    centers = np.array([[a, a, a], [b, b, a], [b, a, b], [a, b, b]])
+    radii = np.full(4, (0.20 * 3.0 / (16.0 * math.pi)) ** (1.0 / 3.0))
+    shape = (n, n, n)
+    phase = spheres_phase(shape, centers, radii)
+    mu, bulk = 28.0, 46.67
+    lam = bulk - 2.0 * mu / 3.0
+    C = np.stack([isotropic_C(mu, lam), isotropic_C(10 * mu, 10 * lam)])
+    mask = mask_uniaxial(0)
+    F_end = np.eye(3)
+    F_end[0, 0] = 1.2
+    return dict(name="paper_particles%d" % n, shape=shape, kind="svk", phase=phase, C=C, mask=mask,
+                target=history_mixed(mask, F_end.reshape(9), nsteps), newton_tol=1e-6, cg_tol=1e-8)
+
+
 def mask_normal_stress_free():
     """Every off-diagonal F component prescribed, the three normal stresses free (P_ii = 0):
     the simple-shear control (the sheared plane is set by the F history)."""
