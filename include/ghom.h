@@ -126,6 +126,22 @@ int ghom_set_tolerances(ghom_ctx *ctx, double newton_tol, double cg_tol, double 
  * the increment counter is not advanced. */
 int ghom_step(ghom_ctx *ctx, ghom_step_info *info);
 
+/* Adaptive stepping (the remedy Sec. 4 names for increments that need many Newton
+ * iterations): advances one load increment like ghom_step, walking it in sub-increments
+ * along which the prescribed values move linearly from those of the current increment to
+ * those of the next.  A sub-increment that ends in GHOM_ENOTCONVERGED, GHOM_ESINGULAR or
+ * GHOM_EDOMAIN is retried from its starting state with half its length, at most max_cuts
+ * times per call (0..30); one that converges within grow_below Newton iterations doubles
+ * the next length.  The next call starts with the length the last one ended with
+ * (ghom_set_history and ghom_load_state reset it to the whole increment).  info (nullable)
+ * sums the iteration counts and CG time of every attempt; *substeps and *cuts (nullable)
+ * receive the accepted sub-increments and the retries.  When the cuts run out the call
+ * returns the last failure's status, F is restored to its value at the start of the
+ * increment and the increment counter is not advanced.  The context keeps two extra
+ * float64 fields (2 x 9 x N) for the restart points, allocated at the first call. */
+int ghom_step_adaptive(ghom_ctx *ctx, int max_cuts, int grow_below, ghom_step_info *info,
+                       int *substeps, int *cuts);
+
 /* Re-solves equilibrium at the current increment without moving the prescribed means
  * (e.g. after ghom_set_stiffness_scale or ghom_load_state).  info as in ghom_step. */
 int ghom_resolve(ghom_ctx *ctx, ghom_step_info *info);

@@ -20,6 +20,7 @@
 
 #include "../../include/ghom.h"
 #include "kernels.hpp"
+#include "substep.hpp"
 
 using namespace ghom;
 
@@ -76,6 +77,7 @@ struct Prob {
   double Favg[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double Pavg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   bool state_valid = false;
+  double adapt_fraction = 1.0;  // adaptive stepping: fraction the next increment starts with
   // solve bookkeeping
   bool running = false;
   int status = GHOM_OK;
@@ -103,6 +105,7 @@ struct Engine {
   CGScalars* sc = nullptr;    // device, one per problem
   double* red = nullptr;      // device, 32 per problem
   int* flags = nullptr;       // device, one per problem
+  double* ckpt = nullptr;        // adaptive stepping: F at the start of the sub-increment and of the increment
   CGScalars* host_sc = nullptr;  // two slots of one entry per problem (slot 0 = latest after a solve)
   hipEvent_t sc_ev[2] = {nullptr, nullptr};
   double* host_red = nullptr;
@@ -709,27 +712,41 @@ void newton(Engine& e, const std::vector<int>& set) {
   }
 }
 
+// Prescribed values of increment k (row k-1 of the history); increment 0 is F = I, P = 0.
+void target_row(const Prob& q, int k, double* out) {
+  for (int i = 0; i < 9; ++i)
+    out[i] = k == 0 ? ((!q.mask[i] && i % 4 == 0) ? 1.0 : 0.0) : q.target[(size_t)(k - 1) * 9 + i];
+}
+
+// Moves problem p's prescribed values from `from` to `to`: the deformation-controlled means
+// shift uniformly by to - from, the stress targets become `to`.  Returns whether F moves.
+bool set_targets(Engine& e, int p, const double* from, const double* to) {
+  Prob& q = e.P[p];
+  ProbDesc& d = e.hdesc[p];
+  bool any = false;
+  for (int i = 0; i < 9; ++i) {
+    d.shift[i] = 0.0;
+    d.pbar[i] = 0.0;
+    if (q.mask[i]) {
+      d.pbar[i] = to[i];
+    } else {
+      d.shift[i] = to[i] - from[i];
+      any = any || d.shift[i] != 0.0;
+    }
+  }
+  if (any) q.state_valid = false;
+  return any;
+}
+
 // Shift the deformation-controlled means to increment k+1 and set the stress targets.
 void begin_increment(Engine& e, const std::vector<int>& set) {
   for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
   for (int p : set) {
     Prob& q = e.P[p];
-    const int k1 = q.k + 1;
-    ProbDesc& d = e.hdesc[p];
-    bool any = false;
-    for (int i = 0; i < 9; ++i) {
-      d.shift[i] = 0.0;
-      d.pbar[i] = 0.0;
-      if (q.mask[i]) {
-        d.pbar[i] = q.target[(size_t)(k1 - 1) * 9 + i];
-      } else {
-        const double prev = (k1 == 1) ? ((i % 4 == 0) ? 1.0 : 0.0) : q.target[(size_t)(k1 - 2) * 9 + i];
-        d.shift[i] = q.target[(size_t)(k1 - 1) * 9 + i] - prev;
-        any = any || d.shift[i] != 0.0;
-      }
-    }
-    d.active = any ? 1 : 0;
-    if (any) q.state_valid = false;
+    double from[9], to[9];
+    target_row(q, q.k, from);
+    target_row(q, q.k + 1, to);
+    e.hdesc[p].active = set_targets(e, p, from, to) ? 1 : 0;
   }
   upload_descs(e);
   for (auto& c : e.C) {
@@ -795,7 +812,7 @@ void destroy_engine(Engine* e) {
       if (c.tw32[a]) (void)hipFree(c.tw32[a]);
     }
   }
-  void* ptrs[] = {e->arena, e->ddesc, e->sc, e->red, e->flags};
+  void* ptrs[] = {e->arena, e->ddesc, e->sc, e->red, e->flags, e->ckpt};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (e->hdesc) (void)hipHostFree(e->hdesc);
@@ -1183,6 +1200,7 @@ int ghom_set_history(ghom_ctx* c, int nsteps, const double* target) {
     Prob& q = c->e->P[0];
     q.target.assign(target, target + 9 * (size_t)nsteps);
     q.nsteps = nsteps;
+    q.adapt_fraction = 1.0;
     return GHOM_OK;
   });
 }
@@ -1214,6 +1232,83 @@ int ghom_step(ghom_ctx* c, ghom_step_info* info) {
     newton(e, {0});
     if (q.status == GHOM_OK || q.status == GHOM_ENOTCONVERGED) q.k += 1;
     return finish_solve(e, 0, info);
+  });
+}
+
+int ghom_step_adaptive(ghom_ctx* c, int max_cuts, int grow_below, ghom_step_info* info, int* substeps,
+                       int* cuts) {
+  return guard(c, [&]() -> int {
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    check_material(q);
+    if (q.nsteps == 0) fail(GHOM_ESTATE, "no history set");
+    if (q.k >= q.nsteps) fail(GHOM_ESTATE, "history exhausted");
+    if (max_cuts < 0 || max_cuts > 30 || grow_below < 0) fail(GHOM_EINVAL, "bad adaptive stepping parameters");
+    const size_t bytes = 9 * (size_t)e.C[q.cls].g.N * sizeof(double);
+    if (!e.ckpt) HIPCALL(hipMalloc((void**)&e.ckpt, 2 * bytes));
+    double* sub0 = e.ckpt;
+    double* inc0 = reinterpret_cast<double*>(reinterpret_cast<char*>(e.ckpt) + bytes);
+    double* F = e.hdesc[0].F;
+    HIPCALL(hipMemcpyAsync(inc0, F, bytes, hipMemcpyDeviceToDevice, e.stream));
+    double from[9], to[9];
+    target_row(q, q.k, from);
+    target_row(q, q.k + 1, to);
+    SubstepClock clk(max_cuts, grow_below, q.adapt_fraction);
+    ghom_step_info tot{};
+    int subs = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (!clk.done()) {
+      double a[9], b[9];
+      lerp9(from, to, clk.theta, a);
+      lerp9(from, to, clk.next_end(), b);
+      HIPCALL(hipMemcpyAsync(sub0, F, bytes, hipMemcpyDeviceToDevice, e.stream));
+      e.hdesc[0].active = set_targets(e, 0, a, b) ? 1 : 0;
+      upload_descs(e);
+      if (e.hdesc[0].active) {
+        ShapeClass& cl = e.C[q.cls];
+        hipLaunchKernelGGL(shift_batch, dim3(cl.vb, 1, 1), dim3(kVoxThreads), 0, e.stream, e.ddesc, cl.ids);
+        HIPCALL(hipGetLastError());
+      }
+      newton(e, {0});
+      tot.newton_iters += q.info.newton_iters;
+      tot.cg_iters_total += q.info.cg_iters_total;
+      tot.cg_breakdowns += q.info.cg_breakdowns;
+      tot.t_cg_ms += q.info.t_cg_ms;
+      tot.crit = q.info.crit;
+      tot.res_rms = q.info.res_rms;
+      if (q.status == GHOM_OK) {
+        clk.accept(q.info.newton_iters);
+        ++subs;
+        continue;
+      }
+      const bool retry = (q.status == GHOM_ENOTCONVERGED || q.status == GHOM_ESINGULAR || q.status == GHOM_EDOMAIN) &&
+                         clk.reject();
+      if (retry) {
+        HIPCALL(hipMemcpyAsync(F, sub0, bytes, hipMemcpyDeviceToDevice, e.stream));
+        q.state_valid = false;
+        continue;
+      }
+      // out of cuts: back to the start of the increment
+      const int st = q.status;
+      const std::string msg = q.msg;
+      HIPCALL(hipMemcpyAsync(F, inc0, bytes, hipMemcpyDeviceToDevice, e.stream));
+      q.state_valid = false;
+      tot.status = st;
+      tot.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (info) *info = tot;
+      if (substeps) *substeps = subs;
+      if (cuts) *cuts = clk.cuts;
+      fail(st, msg + " (adaptive stepping: " + std::to_string(clk.cuts) + " cuts spent; state restored to the start "
+                     "of the increment)");
+    }
+    q.k += 1;
+    q.adapt_fraction = clk.dtheta;
+    tot.status = GHOM_OK;
+    tot.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = tot;
+    if (substeps) *substeps = subs;
+    if (cuts) *cuts = clk.cuts;
+    return GHOM_OK;
   });
 }
 
@@ -1277,6 +1372,7 @@ int ghom_load_state(ghom_ctx* c, const double* F_in, int step) {
     HIPCALL(hipMemcpy(e.hdesc[0].F, F_in, 9 * (size_t)e.C[q.cls].g.N * sizeof(double), hipMemcpyHostToDevice));
     q.k = step;
     q.state_valid = false;
+    q.adapt_fraction = 1.0;
     return GHOM_OK;
   });
 }

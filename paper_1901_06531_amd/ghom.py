@@ -69,6 +69,7 @@ _SIGS = {
     "ghom_set_history": (_i, [_vp, _i, _vp]),
     "ghom_set_tolerances": (_i, [_vp, _d, _d, _d, _i, _i]),
     "ghom_step": (_i, [_vp, ctypes.POINTER(StepInfo)]),
+    "ghom_step_adaptive": (_i, [_vp, _i, _i, ctypes.POINTER(StepInfo), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "ghom_resolve": (_i, [_vp, ctypes.POINTER(StepInfo)]),
     "ghom_get_averages": (_i, [_vp, _vp, _vp]),
     "ghom_get_field": (_i, [_vp, _i, _vp]),
@@ -235,6 +236,18 @@ class Solver:
         rc = lib().ghom_step(self._c, ctypes.byref(info))
         self._check(rc)
         return info.as_dict()
+
+    def step_adaptive(self, max_cuts=8, grow_below=2):
+        """One load increment in sub-increments (ghom_step_adaptive); the info dict also
+        holds 'substeps' and 'cuts'."""
+        info = StepInfo()
+        subs, cuts = ctypes.c_int(), ctypes.c_int()
+        rc = lib().ghom_step_adaptive(self._c, int(max_cuts), int(grow_below), ctypes.byref(info),
+                                      ctypes.byref(subs), ctypes.byref(cuts))
+        self._check(rc)
+        d = info.as_dict()
+        d.update(substeps=subs.value, cuts=cuts.value)
+        return d
 
     def resolve(self):
         info = StepInfo()
