@@ -256,7 +256,7 @@ void launch_xproj_variant(Engine& e, ShapeClass& c, int variant, int role, Slab 
     using S = decltype(s);
     const long long ncols = (long long)c.ny * sl.nkz;
     if (variant == XPROJ_ROWS) {
-      using Cfg = ColCfg<T, S::A, S::B>;
+      using Cfg = XRowsCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
       hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B>), dim3(grid, 3, (unsigned)c.probs.size()), dim3(Cfg::NT), 0,
                          e.stream, e.ddesc, c.ids, role, sl);

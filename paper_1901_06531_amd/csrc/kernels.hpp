@@ -361,11 +361,15 @@ __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* 
 #ifndef GHOM_XPF
 #define GHOM_XPF -1
 #endif
+#ifndef GHOM_XROWS_MAXT
+#define GHOM_XROWS_MAXT 256
+#endif
+template <typename T, int A, int B> using XRowsCfg = ColCfg<T, A, B, 64, GHOM_XROWS_MAXT>;
 template <typename T, int A, int B, bool XPF = (GHOM_XPF < 0 ? sizeof(T) == 4 : GHOM_XPF != 0)>
 __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
                                                 const cx<T>* __restrict__ tw, const ProjParams& pp,
                                                 const CGScalars* __restrict__ sc, int bx, int by) {
-  using Cfg = ColCfg<T, A, B>;
+  using Cfg = XRowsCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
   __shared__ cx<T> lds[Cfg::LDS];
@@ -1144,7 +1148,7 @@ ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int rol
 }
 
 template <typename T, int A, int B>
-__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
+__global__ void __launch_bounds__((XRowsCfg<T, A, B>::NT))
 xproj_rows_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
