@@ -188,7 +188,9 @@ int ghom_residual(ghom_ctx *ctx, const double Pbar[9], double *out_dev);
 enum {
   GHOM_OPT_XPROJ_F64 = 1,  /* x-pass (transform along x + projection) variant, float64    */
   GHOM_OPT_XPROJ_F32 = 2,  /* the same for the float32 transforms of GHOM_FP32_SPLIT      */
-  GHOM_OPT_ZSLABS = 3      /* number of kz slabs the y and x passes are run in (>= 1)     */
+  GHOM_OPT_ZSLABS = 3,     /* number of kz slabs the y and x passes are run in (>= 1)     */
+  GHOM_OPT_GRAPHS = 4      /* 1: CG iterations are captured once into HIP graphs and
+                              replayed (not while profiling is on); 0: launched one by one */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the faster variant by timing

@@ -113,6 +113,8 @@ struct Engine {
   double newton_tol = 1e-6, cg_tol = 1e-8, cg_forcing = 0.0;
   int max_newton = 50, max_cg = 5000;
   int zslabs = 1;
+  bool graphs = false;  // replay captured HIP graphs of CG iterations (not while profiling)
+  std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, first-iteration flag, iterations
   bool prof = false;
   std::map<std::string, ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
@@ -497,17 +499,41 @@ void cg_solve(Engine& e, double* t_ms) {
   int enqueued = 0;
   int chunk = vox >= (1LL << 21) ? 1 : (vox >= (1LL << 18) ? 2 : 8);
   const size_t n = e.P.size();
-  auto enqueue_chunk = [&](int k) {
-    for (int i = 0; i < k; ++i, ++enqueued) {
+  // k CG iterations of every class (the first one starts the solve when `first`); in graph
+  // mode every class is included, since a problem's activity is read by the kernels
+  auto launch_iters = [&](int k, bool first, bool all_classes) {
+    for (int i = 0; i < k; ++i) {
       for (auto& c : e.C) {
-        if (!class_active(e, c)) continue;
-        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, enqueued > 0 ? 1 : 2);
+        if (!all_classes && !class_active(e, c)) continue;
+        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, (first && i == 0) ? 2 : 1);
         timed(e, "cg_scalar", [&] {
           hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
                              c.ids, gz, 2);
         });
       }
     }
+  };
+  auto enqueue_chunk = [&](int k) {
+    const bool first = enqueued == 0;
+    if (e.graphs && !e.prof) {
+      const long long key = ((long long)sizeof(T) << 40) | ((long long)first << 32) | (long long)k;
+      auto it = e.graph_cache.find(key);
+      if (it == e.graph_cache.end()) {
+        hipGraph_t g = nullptr;
+        HIPCALL(hipStreamBeginCapture(e.stream, hipStreamCaptureModeThreadLocal));
+        launch_iters(k, first, true);
+        HIPCALL(hipStreamEndCapture(e.stream, &g));
+        hipGraphExec_t x = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCALL(ie);
+        it = e.graph_cache.emplace(key, x).first;
+      }
+      HIPCALL(hipGraphLaunch(it->second, e.stream));
+    } else {
+      launch_iters(k, first, false);
+    }
+    enqueued += k;
   };
   auto post_status = [&](int slot) {
     HIPCALL(hipMemcpyAsync(e.host_sc + slot * n, e.sc, n * sizeof(CGScalars), hipMemcpyDeviceToHost, e.stream));
@@ -825,6 +851,7 @@ void destroy_engine(Engine* e) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
+  for (auto& kv : e->graph_cache) (void)hipGraphExecDestroy(kv.second);
   for (hipEvent_t ev : e->sc_ev)
     if (ev) (void)hipEventDestroy(ev);
   if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
@@ -1490,6 +1517,13 @@ int ghom_residual(ghom_ctx* c, const double Pbar[9], double* out_dev) {
   });
 }
 
+// captured graphs hold the kernel variants and slab count they were made with
+static void drop_graphs(Engine& e) {
+  if (!e.graph_cache.empty()) sync(e);
+  for (auto& kv : e.graph_cache) (void)hipGraphExecDestroy(kv.second);
+  e.graph_cache.clear();
+}
+
 static int set_option(Engine& e, int key, int value) {
   if (key == GHOM_OPT_XPROJ_F64 || key == GHOM_OPT_XPROJ_F32) {
     if (value < XPROJ_TUNED || value > XPROJ_GROUPS) fail(GHOM_EINVAL, "x-pass variant must be 0, 1 or 2");
@@ -1497,11 +1531,19 @@ static int set_option(Engine& e, int key, int value) {
       cl.xproj_var[key == GHOM_OPT_XPROJ_F64 ? 0 : 1] = value;
       if (value == XPROJ_TUNED) tune_class(e, cl, key == GHOM_OPT_XPROJ_F64 ? 0 : 1);
     }
+    drop_graphs(e);
     return GHOM_OK;
   }
   if (key == GHOM_OPT_ZSLABS) {
     if (value < 1 || value > 4096) fail(GHOM_EINVAL, "slab count must be in [1, 4096]");
     e.zslabs = value;
+    drop_graphs(e);
+    return GHOM_OK;
+  }
+  if (key == GHOM_OPT_GRAPHS) {
+    if (value != 0 && value != 1) fail(GHOM_EINVAL, "graph option must be 0 or 1");
+    e.graphs = value != 0;
+    drop_graphs(e);
     return GHOM_OK;
   }
   fail(GHOM_EINVAL, "unknown option");
@@ -1512,6 +1554,7 @@ static int get_option(Engine& e, int key, int* value) {
   if (key == GHOM_OPT_XPROJ_F64) *value = e.C[0].xproj_var[0];
   else if (key == GHOM_OPT_XPROJ_F32) *value = e.C[0].xproj_var[1];
   else if (key == GHOM_OPT_ZSLABS) *value = e.zslabs;
+  else if (key == GHOM_OPT_GRAPHS) *value = e.graphs ? 1 : 0;
   else fail(GHOM_EINVAL, "unknown option");
   return GHOM_OK;
 }
