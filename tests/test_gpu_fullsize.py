@@ -153,3 +153,56 @@ def test_adjoint128_matches_finite_differences():
             worst = max(worst, abs(fd - grad[v]) / abs(grad[v]))
         say("100 voxels: worst relative difference %.3e" % worst)
         assert worst < 1e-3
+
+
+def test_particles128_mixed_increment_fp32_split_satisfies_oracle_equilibrium():
+    w = synth.workload_particles(n=128)
+    with ghom.Solver(w["shape"], precision=ghom.FP32_SPLIT) as s:
+        s.setup(w)
+        s.set_tolerances(w["newton_tol"], w["cg_tol"], 1e-5)
+        info = s.step()
+        say("gpu increment 1 (fp32-split): newton %d cg %d" % (info["newton_iters"], info["cg_iters_total"]))
+        _equilibrium_checks(w, s, tol_rms=1e-7)
+
+
+def test_full_batch_increment_matches_single_solves_and_oracle_equilibrium():
+    """The 384-problem batch (64 RVEs of 32^3..96^3 x 6 load cases), one increment in
+    FP32-split: a sample of problems (one of each size and load case) equals the same problem
+    solved alone on the GPU bit for bit (same kernel variants), and satisfies the oracle's
+    equilibrium equations."""
+    ws = synth.workload_batch()
+    say("batch of %d problems" % len(ws))
+    with ghom.Batch(ws, precision=ghom.FP32_SPLIT) as b:
+        b.set_tolerances(1e-6, 1e-8, 1e-5)
+        # the same x-pass variant as the single solves below (the autotuner may pick per shape)
+        b.set_option(ghom.OPT_XPROJ_F64, 1)
+        b.set_option(ghom.OPT_XPROJ_F32, 1)
+        infos = b.step()
+        assert all(i["status"] == 0 for i in infos)
+        sample = [k for k in range(len(ws)) if (k // 6) % 16 == 0]  # first RVE of every size, all 6 cases
+        assert len(sample) == 24
+        for k in sample:
+            w = ws[k]
+            Fb, Pb = b.averages(k)
+            Ffield = b.field(k)
+            with ghom.Solver(w["shape"], precision=ghom.FP32_SPLIT) as s:
+                s.setup(w)
+                s.set_tolerances(1e-6, 1e-8, 1e-5)
+                s.set_option(ghom.OPT_XPROJ_F64, 1)
+                s.set_option(ghom.OPT_XPROJ_F32, 1)
+                info = s.step()
+                assert info["newton_iters"] == infos[k]["newton_iters"]
+                assert info["cg_iters_total"] == infos[k]["cg_iters_total"]
+                Fs, Ps = s.averages()
+                assert np.array_equal(Fs, Fb) and np.array_equal(Ps, Pb)
+                assert np.array_equal(s.field(ghom.FIELD_F), Ffield)
+            o = _oracle_for(w)
+            o.set_state(Ffield, 1)
+            Pbar = o.target_stress(1)
+            P = o.stress(Ffield)
+            rms = o.rms(o.residual(P, Pbar))
+            say("  %s: oracle residual rms %.2e" % (w["name"], rms))
+            assert rms < 1e-7
+            mask = np.asarray(w["mask"]) > 0
+            np.testing.assert_allclose(Fb[~mask], w["target"][0][~mask], rtol=0, atol=1e-14)
+            np.testing.assert_allclose(Pb[mask], Pbar[mask], rtol=0, atol=1e-6)
