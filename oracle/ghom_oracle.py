@@ -212,6 +212,45 @@ def svk_tangent_apply(F, C, dF):
     return dF @ S + F @ dS
 
 
+# Finite-strain viscoelasticity (a path- and rate-dependent law with internal variables,
+# eq. 1 of the paper's general setting; the paper's own crystal-plasticity model is not
+# given).  Saint Venant-Kirchhoff form with one relaxing branch: S = Cinf : E + Q, where the
+# overstress Q (symmetric, internal variable) obeys dQ/dt + Q / tau = C1 : dE/dt.  Over an
+# increment of length dt with E linear in time the equation integrates exactly to
+#   Q_{n+1} = a Q_n + b C1 : (E_{n+1} - E_n),  a = exp(-dt/tau),  b = tau (1 - a) / dt,
+# and the algorithmic tangent of S is Cinf + b C1.  E_n and Q_n are the values committed at
+# the end of the previous increment.
+def visco_factors(dt, tau):
+    """a = exp(-dt/tau) and b = tau (1 - a) / dt per voxel (b -> 1 as dt/tau -> 0)."""
+    x = dt / np.asarray(tau, float)
+    a = np.exp(-x)
+    b = np.where(x > 0, -np.expm1(-x) / np.where(x > 0, x, 1.0), 1.0)
+    return a, b
+
+
+def visco_update(F, E_n, Q_n, Cinf, C1, a, b):
+    """E, Q and S at the end of the increment for deformation gradient F."""
+    E = _green_lagrange(F)
+    Q = a[:, None, None] * Q_n + b[:, None, None] * np.einsum("nijkl,nkl->nij", C1, E - E_n)
+    S = np.einsum("nijkl,nkl->nij", Cinf, E) + Q
+    return E, Q, S
+
+
+def visco_stress(F, E_n, Q_n, Cinf, C1, a, b):
+    """P = F S of the viscoelastic law at the end of the increment."""
+    return F @ visco_update(F, E_n, Q_n, Cinf, C1, a, b)[2]
+
+
+def visco_tangent_apply(F, E_n, Q_n, Cinf, C1, a, b, dF):
+    """K : dF = dF S + F ((Cinf + b C1) : sym(F^T dF)), the derivative of visco_stress in F
+    at fixed E_n, Q_n and dt."""
+    S = visco_update(F, E_n, Q_n, Cinf, C1, a, b)[2]
+    FtdF = F.transpose(0, 2, 1) @ dF
+    dE = 0.5 * (FtdF + FtdF.transpose(0, 2, 1))
+    dS = np.einsum("nijkl,nkl->nij", Cinf, dE) + b[:, None, None] * np.einsum("nijkl,nkl->nij", C1, dE)
+    return dF @ S + F @ dS
+
+
 # --------------------------------------------------------------------------------------
 # The solver: Newton (eq. 4, 20) with conjugate gradients on G*(K : dF) (Sec. 2.2-2.3)
 # --------------------------------------------------------------------------------------
@@ -251,6 +290,7 @@ class Oracle:
         self.max_newton = 50
         self.max_cg = 5000
         self.k = 0
+        self.dt = 1.0
         self.cg_breakdowns = 0
         self.F = np.tile(EYE9[:, None], (1, self.N)).reshape((9,) + self.shape)
         self.history: list[StepRecord] = []
@@ -267,6 +307,22 @@ class Oracle:
         self.kind = "svk"
         self.phase = np.asarray(phase).reshape(-1).astype(np.int64)
         self.C_tab = np.asarray(C, dtype=float).reshape(-1, 3, 3, 3, 3)
+
+    def set_material_visco(self, phase, Cinf, C1, tau):
+        """Viscoelastic law (see visco_update): per-phase equilibrium stiffness Cinf, branch
+        stiffness C1 (each (nphase, 3, 3, 3, 3) or (nphase, 81)) and relaxation time tau.
+        The internal variables start at E_n = Q_n = 0."""
+        self.kind = "visco"
+        self.phase = np.asarray(phase).reshape(-1).astype(np.int64)
+        self.Cinf_tab = np.asarray(Cinf, dtype=float).reshape(-1, 3, 3, 3, 3)
+        self.C1_tab = np.asarray(C1, dtype=float).reshape(-1, 3, 3, 3, 3)
+        self.tau_tab = np.asarray(tau, dtype=float).reshape(-1)
+        self.E_n = np.zeros((self.N, 3, 3))
+        self.Q_n = np.zeros((self.N, 3, 3))
+
+    def set_time_step(self, dt):
+        """Length of every load increment (rate-dependent laws only)."""
+        self.dt = float(dt)
 
     def set_stiffness_scale(self, s):
         """Per-voxel factor s(x) > 0 multiplying every modulus of the voxel's phase."""
@@ -299,6 +355,10 @@ class Oracle:
         s = self.scale[sl]
         if self.kind == "nh":
             return self.mu_tab[ph] * s, self.lam_tab[ph] * s
+        if self.kind == "visco":
+            a, b = visco_factors(self.dt, self.tau_tab[ph])
+            return (self.E_n[sl], self.Q_n[sl], self.Cinf_tab[ph] * s[:, None, None, None, None],
+                    self.C1_tab[ph] * s[:, None, None, None, None], a, b)
         return (self.C_tab[ph] * s[:, None, None, None, None],)
 
     def stress(self, F9=None) -> np.ndarray:
@@ -307,7 +367,12 @@ class Oracle:
         out = np.empty_like(Fv)
         for sl in self._chunks():
             args = self._mat_args(sl)
-            out[sl] = nh_stress(Fv[sl], *args) if self.kind == "nh" else svk_stress(Fv[sl], *args)
+            if self.kind == "nh":
+                out[sl] = nh_stress(Fv[sl], *args)
+            elif self.kind == "visco":
+                out[sl] = visco_stress(Fv[sl], *args)
+            else:
+                out[sl] = svk_stress(Fv[sl], *args)
         return _field(out, self.shape)
 
     def tangent_apply(self, dF9, F9=None) -> np.ndarray:
@@ -319,6 +384,8 @@ class Oracle:
             args = self._mat_args(sl)
             if self.kind == "nh":
                 out[sl] = nh_tangent_apply(Fv[sl], *args, dv[sl])
+            elif self.kind == "visco":
+                out[sl] = visco_tangent_apply(Fv[sl], *args, dv[sl])
             else:
                 out[sl] = svk_tangent_apply(Fv[sl], *args, dv[sl])
         return _field(out, self.shape)
@@ -400,8 +467,20 @@ class Oracle:
         self.F = self.F + shift.reshape(9, 1, 1, 1)
         rec = self.newton(Pbar)
         self.k = k
+        if self.kind == "visco":
+            self.commit()
         self.history.append(rec)
         return rec
+
+    def commit(self):
+        """End of an increment of the viscoelastic law: E_n and Q_n take their values at
+        the converged F."""
+        Fv = _voxels(self.F)
+        E_new = np.empty_like(self.E_n)
+        Q_new = np.empty_like(self.Q_n)
+        for sl in self._chunks():
+            E_new[sl], Q_new[sl], _ = visco_update(Fv[sl], *self._mat_args(sl))
+        self.E_n, self.Q_n = E_new, Q_new
 
     def target_stress(self, k=None):
         """P-bar of increment k (default: the current one) on the stress-controlled
@@ -440,7 +519,10 @@ class Oracle:
                 break
         if not converged:
             raise NotConvergedError("Newton reached max_newton=%d (crit %.3e)" % (self.max_newton, crit))
-        Favg, Pavg = self.averages()
+        # P at the converged F (for a path-dependent law: before the internal variables are
+        # committed at the end of the increment)
+        self.P_last = self.stress()
+        Favg, Pavg = self.averages(P9=self.P_last)
         return StepRecord(Favg, Pavg, newton, cg_total, per, crit)
 
     # ---- adjoint ---------------------------------------------------------------------
@@ -453,6 +535,8 @@ class Oracle:
         the range of G*), dJ/ds(x) = -lam(x) : dP/ds(x) = -lam(x) : P(x) / s(x), because
         every modulus is proportional to s.
         """
+        if self.kind == "visco":
+            raise OracleError("the adjoint here is for path-independent (hyperelastic) laws")
         g = np.broadcast_to(np.asarray(a9, float).reshape(9, 1, 1, 1) / self.N, (9,) + self.shape)
         rhs = apply_projection(np.ascontiguousarray(g), self.mask, self.lengths)
         lam, _ = self.conjugate_gradient(rhs)
