@@ -98,6 +98,27 @@ int ghom_set_material_neohookean(ghom_ctx *ctx, const uint16_t *phase, int nphas
  * Resets the deformation to F = I and the increment to 0. */
 int ghom_set_material_svk(ghom_ctx *ctx, const uint16_t *phase, int nphase, const double *C);
 
+/* Viscoelastic phases: a path- and rate-dependent law with internal variables (the
+ * general setting of eq. 1; the paper's own crystal-plasticity model is not given).
+ * Saint Venant-Kirchhoff form with one relaxing branch: S = Cinf : E + Q, P = F S, where the
+ * overstress Q obeys dQ/dt + Q / tau = C1 : dE/dt.  Over each load increment of length dt
+ * (ghom_set_time_step) E is taken linear in time, which integrates exactly to
+ * Q = a Q_n + b C1 : (E - E_n), a = exp(-dt/tau), b = tau (1 - a) / dt, with E_n and Q_n the
+ * values committed at the end of the previous increment; the Newton tangent is the
+ * Saint Venant-Kirchhoff one with the stiffness Cinf + b C1.  Cinf and C1 (host): nphase
+ * stiffness tensors of 81 values each, as for ghom_set_material_svk; tau (host): nphase
+ * relaxation times > 0.  The internal variables start at zero; a converged (or
+ * ENOTCONVERGED) increment commits them.  Resets the deformation to F = I and the increment
+ * to 0.  With this law ghom_resolve and ghom_adjoint_grad_scale return GHOM_EINVAL, and
+ * ghom_load_state accepts step 0 only (it also zeroes the internal variables); the batch
+ * API does not take it.  The context keeps 12 more float64 planes (E_n, Q_n). */
+int ghom_set_material_visco(ghom_ctx *ctx, const uint16_t *phase, int nphase, const double *Cinf,
+                            const double *C1, const double *tau);
+
+/* Length of every load increment for rate-dependent laws (default 1; ghom_step_adaptive
+ * gives each sub-increment its share).  Must be finite and > 0. */
+int ghom_set_time_step(ghom_ctx *ctx, double dt);
+
 /* Per-voxel stiffness scale s(x) > 0 multiplying every modulus of the voxel (host, N
  * values; NULL restores s = 1).  Used by ghom_adjoint_grad_scale. */
 int ghom_set_stiffness_scale(ghom_ctx *ctx, const double *s);

@@ -84,10 +84,15 @@ struct Prob {
   std::string msg;
   double rms_b = 0.0;
   ghom_step_info info{};
+  // viscoelastic law: Voigt tables of Cinf and C1 and tau per phase, increment length
+  std::vector<double> vinf, v1, vtau;
+  double dt = 1.0;
   // device buffers owned outside the arena
   double* scale = nullptr;
   double* mat = nullptr;
   float* mat32 = nullptr;
+  double* visc = nullptr;  // viscoelastic law: Cinf, C1, a, b per phase
+  double* iv = nullptr;    // viscoelastic law: internal variables (kViscoIV x N)
 };
 
 struct Engine {
@@ -363,7 +368,8 @@ int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
   const std::string t = tname<T>();
   int gz;
   if (c.kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p, "op_zfwd_" + t);
-  else gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
+  else if (c.kind == MAT_SVK) gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
+  else gz = launch_zfwd<T, Z_VISCO, T>(e, c, role, update_p, "op_zfwd_" + t);
   if (role == ROLE_OP_CG) {
     timed(e, "cg_scalar", [&] {
       hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
@@ -392,11 +398,18 @@ void constitutive(Engine& e) {
           hipLaunchKernelGGL((constitutive_batch<double, MAT_NH>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
         else
           hipLaunchKernelGGL((constitutive_batch<float, MAT_NH>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
-      } else {
+      } else if (c.kind == MAT_SVK) {
         if (e.prec == GHOM_FP64)
           hipLaunchKernelGGL((constitutive_batch<double, MAT_SVK>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
         else
           hipLaunchKernelGGL((constitutive_batch<float, MAT_SVK>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
+      } else {
+        if (e.prec == GHOM_FP64)
+          hipLaunchKernelGGL((constitutive_batch<double, MAT_VISCO>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc,
+                             c.ids);
+        else
+          hipLaunchKernelGGL((constitutive_batch<float, MAT_VISCO>), grid, dim3(kVoxThreads), 0, e.stream, e.ddesc,
+                             c.ids);
       }
     });
     timed(e, "reduce", [&] {
@@ -440,9 +453,12 @@ void constitutive_residual(Engine& e) {
     if (c.kind == MAT_NH) {
       if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_NH, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
       else gz = launch_zfwd<double, Z_CONST_NH, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
-    } else {
+    } else if (c.kind == MAT_SVK) {
       if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_SVK, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
       else gz = launch_zfwd<double, Z_CONST_SVK, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+    } else {
+      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_VISCO, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+      else gz = launch_zfwd<double, Z_CONST_VISCO, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
     }
     timed(e, "reduce", [&] {
       hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gz, 18, 0, 1, 0);
@@ -811,6 +827,12 @@ void reset_state(Engine& e, const std::vector<int>& set) {
                        c.ids, 0);
     HIPCALL(hipGetLastError());
   }
+  for (int p : set)
+    if (e.P[p].iv) {
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, (long long)kViscoIV * e.C[e.P[p].cls].g.N,
+                         e.P[p].iv);
+      HIPCALL(hipGetLastError());
+    }
   sync(e);
 }
 
@@ -830,6 +852,8 @@ void destroy_engine(Engine* e) {
     if (q.scale) (void)hipFree(q.scale);
     if (q.mat) (void)hipFree(q.mat);
     if (q.mat32) (void)hipFree(q.mat32);
+    if (q.visc) (void)hipFree(q.visc);
+    if (q.iv) (void)hipFree(q.iv);
   }
   for (auto& c : e->C) {
     if (c.ids) (void)hipFree(c.ids);
@@ -1034,7 +1058,7 @@ void set_material(Engine& e, int p, int kind, const uint16_t* phase, int nphase,
   q.mat32 = nullptr;
   HIPCALL(hipMalloc((void**)&q.mat, tab.size() * sizeof(double)));
   HIPCALL(hipMemcpy(q.mat, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-  if (kind == MAT_SVK) {
+  if (kind != MAT_NH) {
     std::vector<float> t32(tab.begin(), tab.end());
     HIPCALL(hipMalloc((void**)&q.mat32, t32.size() * sizeof(float)));
     HIPCALL(hipMemcpy(q.mat32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -1048,6 +1072,45 @@ void set_material(Engine& e, int p, int kind, const uint16_t* phase, int nphase,
   e.hdesc[p].mat32 = q.mat32;
   c.kind = kind;
   reset_state(e, {p});
+}
+
+// Viscoelastic law, increment of length dt_eff: the per-phase device table (Cinf, C1,
+// a = exp(-dt/tau), b = tau (1 - a) / dt) and the algorithmic stiffness Cinf + b C1 the
+// tangent uses (float64 and float32 copies).
+void visco_tables(Engine& e, int p, double dt_eff) {
+  Prob& q = e.P[p];
+  const int np = q.nphase;
+  std::vector<double> vt((size_t)kViscoTable * np), calg(36 * (size_t)np);
+  for (int ph = 0; ph < np; ++ph) {
+    const double x = dt_eff / q.vtau[ph];
+    const double a = std::exp(-x);
+    const double b = x > 0.0 ? -std::expm1(-x) / x : 1.0;
+    double* t = &vt[(size_t)kViscoTable * ph];
+    for (int k = 0; k < 36; ++k) {
+      t[k] = q.vinf[36 * (size_t)ph + k];
+      t[36 + k] = q.v1[36 * (size_t)ph + k];
+      calg[36 * (size_t)ph + k] = t[k] + b * t[36 + k];
+    }
+    t[72] = a;
+    t[73] = b;
+  }
+  std::vector<float> c32(calg.begin(), calg.end());
+  sync(e);
+  HIPCALL(hipMemcpy(q.visc, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCALL(hipMemcpy(q.mat, calg.data(), calg.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCALL(hipMemcpy(q.mat32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+  q.state_valid = false;
+}
+
+// End of an accepted increment of the viscoelastic law for problem p (F converged).
+void visco_commit(Engine& e, int p) {
+  for (size_t i = 0; i < e.P.size(); ++i) e.hdesc[i].active = (int)i == p ? 1 : 0;
+  upload_descs(e);
+  ShapeClass& c = e.C[e.P[p].cls];
+  hipLaunchKernelGGL(visco_commit_batch, dim3(c.vb, 1, (unsigned)c.probs.size()), dim3(kVoxThreads), 0, e.stream,
+                     e.ddesc, c.ids);
+  HIPCALL(hipGetLastError());
+  // P and the averages stay those of the converged increment
 }
 
 void refresh_averages(Engine& e, int p) {
@@ -1181,6 +1244,43 @@ int ghom_set_material_svk(ghom_ctx* c, const uint16_t* phase, int nphase, const 
   });
 }
 
+int ghom_set_material_visco(ghom_ctx* c, const uint16_t* phase, int nphase, const double* Cinf, const double* C1,
+                            const double* tau) {
+  return guard(c, [&]() -> int {
+    if (!phase || !Cinf || !C1 || !tau || nphase < 1 || nphase > 65536)
+      fail(GHOM_EINVAL, "bad viscoelastic arguments");
+    for (int i = 0; i < nphase; ++i)
+      if (!(tau[i] > 0.0) || !std::isfinite(tau[i])) fail(GHOM_EINVAL, "relaxation times must be finite and > 0");
+    Engine& e = *c->e;
+    Prob& q = e.P[0];
+    std::vector<double> vinf = voigt_table(Cinf, nphase), v1 = voigt_table(C1, nphase);
+    const size_t N = (size_t)e.C[q.cls].g.N;
+    sync(e);
+    if (q.visc) HIPCALL(hipFree(q.visc));
+    q.visc = nullptr;
+    HIPCALL(hipMalloc((void**)&q.visc, (size_t)kViscoTable * nphase * sizeof(double)));
+    if (!q.iv) HIPCALL(hipMalloc((void**)&q.iv, (size_t)kViscoIV * N * sizeof(double)));
+    q.vinf = vinf;
+    q.v1 = v1;
+    q.vtau.assign(tau, tau + nphase);
+    e.hdesc[0].visc = q.visc;
+    e.hdesc[0].iv = q.iv;
+    set_material(e, 0, MAT_VISCO, phase, nphase, vinf);  // also zeroes F - I and the internal variables
+    visco_tables(e, 0, q.dt);
+    return GHOM_OK;
+  });
+}
+
+int ghom_set_time_step(ghom_ctx* c, double dt) {
+  return guard(c, [&]() -> int {
+    if (!(dt > 0.0) || !std::isfinite(dt)) fail(GHOM_EINVAL, "the time step must be finite and > 0");
+    Engine& e = *c->e;
+    e.P[0].dt = dt;
+    if (e.P[0].kind == MAT_VISCO) visco_tables(e, 0, dt);
+    return GHOM_OK;
+  });
+}
+
 int ghom_set_stiffness_scale(ghom_ctx* c, const double* s) {
   return guard(c, [&]() -> int {
     Engine& e = *c->e;
@@ -1255,9 +1355,13 @@ int ghom_step(ghom_ctx* c, ghom_step_info* info) {
     check_material(q);
     if (q.nsteps == 0) fail(GHOM_ESTATE, "no history set");
     if (q.k >= q.nsteps) fail(GHOM_ESTATE, "history exhausted");
+    if (q.kind == MAT_VISCO) visco_tables(e, 0, q.dt);
     begin_increment(e, {0});
     newton(e, {0});
-    if (q.status == GHOM_OK || q.status == GHOM_ENOTCONVERGED) q.k += 1;
+    if (q.status == GHOM_OK || q.status == GHOM_ENOTCONVERGED) {
+      if (q.kind == MAT_VISCO) visco_commit(e, 0);
+      q.k += 1;
+    }
     return finish_solve(e, 0, info);
   });
 }
@@ -1289,6 +1393,7 @@ int ghom_step_adaptive(ghom_ctx* c, int max_cuts, int grow_below, ghom_step_info
       lerp9(from, to, clk.theta, a);
       lerp9(from, to, clk.next_end(), b);
       HIPCALL(hipMemcpyAsync(sub0, F, bytes, hipMemcpyDeviceToDevice, e.stream));
+      if (q.kind == MAT_VISCO) visco_tables(e, 0, (clk.next_end() - clk.theta) * q.dt);
       e.hdesc[0].active = set_targets(e, 0, a, b) ? 1 : 0;
       upload_descs(e);
       if (e.hdesc[0].active) {
@@ -1304,6 +1409,7 @@ int ghom_step_adaptive(ghom_ctx* c, int max_cuts, int grow_below, ghom_step_info
       tot.crit = q.info.crit;
       tot.res_rms = q.info.res_rms;
       if (q.status == GHOM_OK) {
+        if (q.kind == MAT_VISCO) visco_commit(e, 0);
         clk.accept(q.info.newton_iters);
         ++subs;
         continue;
@@ -1343,6 +1449,8 @@ int ghom_resolve(ghom_ctx* c, ghom_step_info* info) {
   return guard(c, [&]() -> int {
     Engine& e = *c->e;
     check_material(e.P[0]);
+    if (e.P[0].kind == MAT_VISCO)
+      fail(GHOM_EINVAL, "re-solving an increment needs a path-independent law (the viscoelastic state has moved on)");
     set_pbar_current(e, 0);
     newton(e, {0});
     return finish_solve(e, 0, info);
@@ -1395,8 +1503,14 @@ int ghom_load_state(ghom_ctx* c, const double* F_in, int step) {
     Prob& q = e.P[0];
     if (!F_in || step < 0 || (q.nsteps > 0 && step > q.nsteps) || (q.nsteps == 0 && step != 0))
       fail(GHOM_EINVAL, "bad state");
+    if (q.kind == MAT_VISCO && step != 0)
+      fail(GHOM_EINVAL, "the viscoelastic law's internal variables are not part of a saved state: only step 0 loads");
     sync(e);
     HIPCALL(hipMemcpy(e.hdesc[0].F, F_in, 9 * (size_t)e.C[q.cls].g.N * sizeof(double), hipMemcpyHostToDevice));
+    if (q.kind == MAT_VISCO) {
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, (long long)kViscoIV * e.C[q.cls].g.N, q.iv);
+      HIPCALL(hipGetLastError());
+    }
     q.k = step;
     q.state_valid = false;
     q.adapt_fraction = 1.0;
@@ -1410,6 +1524,7 @@ int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
     Prob& q = e.P[0];
     check_material(q);
     if (!a || !grad_out) fail(GHOM_EINVAL, "null argument");
+    if (q.kind == MAT_VISCO) fail(GHOM_EINVAL, "the adjoint is for path-independent (hyperelastic) laws");
     const long long N = e.C[q.cls].g.N;
     // right-hand side G*(a) of a uniform a: only xi = 0 content, kept on the
     // stress-controlled components (the 1/N of G*(a/N) is applied to the solution)

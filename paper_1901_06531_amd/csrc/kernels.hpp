@@ -37,10 +37,17 @@ struct Slab {
   int kz0, nkz;
 };
 
-enum { MAT_NH = 1, MAT_SVK = 2 };
-constexpr int kNHState = 12;   // F^-T (9), a = s mu, b = s lam, c = s (mu - lam ln J)
-constexpr int kSVKState = 10;  // H = F - I (9), s (1)
-constexpr int kStatePlanes = kNHState > kSVKState ? kNHState : kSVKState;
+enum { MAT_NH = 1, MAT_SVK = 2, MAT_VISCO = 3 };
+constexpr int kNHState = 12;     // F^-T (9), a = s mu, b = s lam, c = s (mu - lam ln J)
+constexpr int kSVKState = 10;    // H = F - I (9), s (1)
+constexpr int kViscoState = 16;  // H = F - I (9), S in Voigt order (6), s (1)
+constexpr int kStatePlanes = kViscoState;
+static_assert(kStatePlanes >= kNHState && kStatePlanes >= kSVKState, "state planes");
+// viscoelastic law: per phase Cinf (36), C1 (36), a = exp(-dt/tau), b = tau (1 - a) / dt
+constexpr int kViscoTable = 74;
+// internal variables of the viscoelastic law, float64 planes: E_n (6, Voigt with engineering
+// shears), Q_n (6, Voigt)
+constexpr int kViscoIV = 12;
 
 // scalars shared by the CG kernels (device memory)
 struct CGScalars {
@@ -529,13 +536,46 @@ __device__ __forceinline__ void tangent_svk(const T* H, T s, const T* __restrict
     }
 }
 
+// tangent of the viscoelastic law: K : d = d S + F (s C : sym(F^T d)), F = I + H, with the
+// stress S taken from the state and C the algorithmic stiffness Cinf + b C1 of the increment
+template <typename T>
+__device__ __forceinline__ void tangent_visco(const T* H, const T* S, T s, const T* __restrict__ C6, const T* d, T* out) {
+  auto ftd = [&](int i, int j) { return d[3 * i + j] + H[i] * d[j] + H[3 + i] * d[3 + j] + H[6 + i] * d[6 + j]; };
+  T dE[6];
+  dE[0] = ftd(0, 0);
+  dE[1] = ftd(1, 1);
+  dE[2] = ftd(2, 2);
+  dE[3] = ftd(1, 2) + ftd(2, 1);
+  dE[4] = ftd(0, 2) + ftd(2, 0);
+  dE[5] = ftd(0, 1) + ftd(1, 0);
+  T dS[6];
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    T acc = 0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) acc += C6[6 * I + J] * dE[J];
+    dS[I] = s * acc;
+  }
+  const T Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
+  const T dSm[9] = {dS[0], dS[5], dS[4], dS[5], dS[1], dS[3], dS[4], dS[3], dS[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T acc = dSm[3 * i + j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += d[3 * i + k] * Sm[3 * k + j] + H[3 * i + k] * dSm[3 * k + j];
+      out[3 * i + j] = acc;
+    }
+}
+
 // Constitutive update of one voxel in float64 (neo-Hookean or SVK, modulus scale s):
 // P(F) into p, the tangent state into planes of N values at voxel v (CG type TS).
 // Returns false when det F <= 0.
 template <typename TS, int KIND>
 __device__ __forceinline__ bool constitutive_point(const double* f, int ph, double s, bool has_scale,
                                                    const double* __restrict__ mat, double* p, TS* __restrict__ state,
-                                                   long long N, long long v) {
+                                                   long long N, long long v, const double* __restrict__ iv = nullptr) {
   const double cf0 = f[4] * f[8] - f[5] * f[7];
   const double cf1 = f[5] * f[6] - f[3] * f[8];
   const double cf2 = f[3] * f[7] - f[4] * f[6];
@@ -562,6 +602,44 @@ __device__ __forceinline__ bool constitutive_point(const double* f, int ph, doub
     state[9 * N + v] = (TS)mu;
     state[10 * N + v] = (TS)lam;
     state[11 * N + v] = (TS)(mu - lam * lnJ);
+  } else if constexpr (KIND == MAT_VISCO) {
+    // S = s Cinf : E + Q, Q = a Q_n + b s C1 : (E - E_n) (exact over the increment for E
+    // linear in time); the tangent state keeps S, since it is not a function of F alone
+    const double* t = mat + kViscoTable * ph;
+    const double a = t[72], b = t[73];
+    auto ftf = [&](int i, int j) { return f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j]; };
+    double E[6];
+    E[0] = 0.5 * (ftf(0, 0) - 1.0);
+    E[1] = 0.5 * (ftf(1, 1) - 1.0);
+    E[2] = 0.5 * (ftf(2, 2) - 1.0);
+    E[3] = ftf(1, 2);
+    E[4] = ftf(0, 2);
+    E[5] = ftf(0, 1);
+    double dE[6];
+#pragma unroll
+    for (int J = 0; J < 6; ++J) dE[J] = E[J] - iv[J * N + v];
+    double S[6];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      double ci = 0.0, c1 = 0.0;
+#pragma unroll
+      for (int J = 0; J < 6; ++J) {
+        ci += t[6 * I + J] * E[J];
+        c1 += t[36 + 6 * I + J] * dE[J];
+      }
+      S[I] = s * ci + a * iv[(6 + I) * N + v] + b * s * c1;
+    }
+    const double Sm[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        p[3 * i + j] = f[3 * i] * Sm[j] + f[3 * i + 1] * Sm[3 + j] + f[3 * i + 2] * Sm[6 + j];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) state[c * N + v] = (TS)(c % 4 == 0 ? f[c] - 1.0 : f[c]);
+#pragma unroll
+    for (int I = 0; I < 6; ++I) state[(9 + I) * N + v] = (TS)S[I];
+    if (has_scale) state[15 * N + v] = (TS)s;
   } else {
     const double* C6 = mat + 36 * ph;
     // E = (F^T F - I)/2 in Voigt with engineering shears
@@ -600,7 +678,7 @@ __device__ __forceinline__ bool constitutive_point(const double* f, int ph, doub
 // Z_CONST_*: the forward pass of the Newton residual with the constitutive update fused
 // in: F -> P (written), tangent state (written, CG type TIN), sums of F and P per block,
 // and P goes into the transform.
-enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2, Z_CONST_NH = 3, Z_CONST_SVK = 4 };
+enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2, Z_CONST_NH = 3, Z_CONST_SVK = 4, Z_VISCO = 5, Z_CONST_VISCO = 6 };
 
 template <typename T, typename TIN>
 struct ZfwdArgs {
@@ -623,6 +701,7 @@ struct ZfwdArgs {
   TIN* state_out;             // tangent state out
   const double* scale;        // per-voxel modulus scale (nullable)
   const double* mat;          // per-phase material table (float64)
+  const double* iv;           // viscoelastic law: internal variables of the last increment
   int* flag;                  // set when det F <= 0 somewhere
   int pstride;                // Z_CONST sums: column k of block bx at partials[k * pstride + bx]
 };
@@ -633,8 +712,9 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
-  constexpr bool CONST = MODE == Z_CONST_NH || MODE == Z_CONST_SVK;
-  constexpr bool CG = MODE == Z_NH || MODE == Z_SVK;
+  constexpr bool CONST = MODE == Z_CONST_NH || MODE == Z_CONST_SVK || MODE == Z_CONST_VISCO;
+  constexpr bool CG = MODE == Z_NH || MODE == Z_SVK || MODE == Z_VISCO;
+  constexpr int KIND = MODE == Z_CONST_NH ? MAT_NH : (MODE == Z_CONST_SVK ? MAT_SVK : MAT_VISCO);
   if (args.sc && args.sc->done) return;
   const long long nlines = (long long)g.nx * g.ny;
   const long long line0 = (long long)bx * (2 * LP);
@@ -660,8 +740,8 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
 #pragma unroll
         for (int c = 0; c < 9; ++c) f[c] = args.F[c * g.N + vox];
         const double sv = args.scale ? args.scale[vox] : 1.0;
-        if (!constitutive_point<TIN, MODE == Z_CONST_NH ? MAT_NH : MAT_SVK>(f, args.phase[vox], sv, args.scale != nullptr,
-                                                                            args.mat, pv, args.state_out, g.N, vox))
+        if (!constitutive_point<TIN, KIND>(f, args.phase[vox], sv, args.scale != nullptr, args.mat, pv, args.state_out,
+                                           g.N, vox, args.iv))
           bad = 1;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
@@ -697,12 +777,20 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
 #pragma unroll
           for (int k = 0; k < kNHState; ++k) st[k] = args.state[k * g.N + vox];
           tangent_nh(st, d, val);
-        } else {
+        } else if constexpr (MODE == Z_SVK) {
           T H[9];
 #pragma unroll
           for (int k = 0; k < 9; ++k) H[k] = args.state[k * g.N + vox];
           const T sv = args.has_scale ? args.state[9 * g.N + vox] : (T)1;
           tangent_svk(H, sv, args.C6 + 36 * args.phase[vox], d, val);
+        } else {
+          T H[9], S[6];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) H[k] = args.state[k * g.N + vox];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) S[k] = args.state[(9 + k) * g.N + vox];
+          const T sv = args.has_scale ? args.state[15 * g.N + vox] : (T)1;
+          tangent_visco(H, S, sv, args.C6 + 36 * args.phase[vox], d, val);
         }
         if (args.partials) {
 #pragma unroll
@@ -892,8 +980,8 @@ template <typename TS, int KIND>
 __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __restrict__ F, double* __restrict__ P,
                                                   TS* __restrict__ state, const uint16_t* __restrict__ phase,
                                                   const double* __restrict__ scale, const double* __restrict__ mat,
-                                                  double* __restrict__ partials, int* __restrict__ flag, int bx,
-                                                  int gx) {
+                                                  const double* __restrict__ iv, double* __restrict__ partials,
+                                                  int* __restrict__ flag, int bx, int gx) {
   double sums[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) sums[k] = 0.0;
@@ -903,7 +991,7 @@ __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __
     double f[9], p[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) f[c] = F[c * g.N + v];
-    if (!constitutive_point<TS, KIND>(f, phase[v], scale ? scale[v] : 1.0, scale != nullptr, mat, p, state, g.N, v))
+    if (!constitutive_point<TS, KIND>(f, phase[v], scale ? scale[v] : 1.0, scale != nullptr, mat, p, state, g.N, v, iv))
       bad = 1;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -1074,8 +1162,10 @@ struct ProbDesc {
   void *x, *r, *p, *state, *H;
   const uint16_t* phase;
   const double* scale;
-  const double* mat;
-  const float* mat32;
+  const double* mat;   // tangent table (float64): neo-Hookean (mu, lam), SVK / viscoelastic 6x6 Voigt
+  const float* mat32;  // the 6x6 tables in float32
+  const double* visc;  // viscoelastic law: per-phase Cinf, C1, a, b (kViscoTable each)
+  double* iv;          // viscoelastic law: E_n, Q_n planes (kViscoIV x N)
   const cx<double>* tw64[3];
   const cx<float>* tw32[3];
   double* partials;  // this problem's partial sums
@@ -1105,13 +1195,14 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   ZfwdArgs<T, TIN> a{};
-  if constexpr (MODE == Z_CONST_NH || MODE == Z_CONST_SVK) {
+  if constexpr (MODE == Z_CONST_NH || MODE == Z_CONST_SVK || MODE == Z_CONST_VISCO) {
     a.F = d.F;
     a.P = d.P;
     a.state_out = reinterpret_cast<TIN*>(d.state);
     a.phase = d.phase;
     a.scale = d.has_scale ? d.scale : nullptr;
-    a.mat = d.mat;
+    a.mat = MODE == Z_CONST_VISCO ? d.visc : d.mat;
+    a.iv = d.iv;
     a.flag = d.flag;
     a.partials = d.partials;
     a.pstride = (int)gridDim.x;
@@ -1199,7 +1290,43 @@ constitutive_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) 
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   constitutive_body<TS, KIND>(d.g, d.F, d.P, reinterpret_cast<TS*>(d.state), d.phase, d.has_scale ? d.scale : nullptr,
-                              d.mat, d.partials, d.flag, blockIdx.x, gridDim.x);
+                              KIND == MAT_VISCO ? d.visc : d.mat, d.iv, d.partials, d.flag, blockIdx.x, gridDim.x);
+}
+
+// End of an accepted increment of the viscoelastic law: E_n <- E(F), Q_n <- a Q_n +
+// b s C1 : (E - E_n) at the converged F
+__global__ void __launch_bounds__(kVoxThreads)
+visco_commit_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const long long N = d.g.N;
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+    double f[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) f[c] = d.F[c * N + v];
+    const double s = d.has_scale ? d.scale[v] : 1.0;
+    const double* t = d.visc + kViscoTable * d.phase[v];
+    auto ftf = [&](int i, int j) { return f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j]; };
+    double E[6];
+    E[0] = 0.5 * (ftf(0, 0) - 1.0);
+    E[1] = 0.5 * (ftf(1, 1) - 1.0);
+    E[2] = 0.5 * (ftf(2, 2) - 1.0);
+    E[3] = ftf(1, 2);
+    E[4] = ftf(0, 2);
+    E[5] = ftf(0, 1);
+    double dE[6];
+#pragma unroll
+    for (int J = 0; J < 6; ++J) dE[J] = E[J] - d.iv[J * N + v];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      double c1 = 0.0;
+#pragma unroll
+      for (int J = 0; J < 6; ++J) c1 += t[36 + 6 * I + J] * dE[J];
+      d.iv[(6 + I) * N + v] = t[72] * d.iv[(6 + I) * N + v] + t[73] * s * c1;
+    }
+#pragma unroll
+    for (int J = 0; J < 6; ++J) d.iv[J * N + v] = E[J];
+  }
 }
 
 

@@ -65,6 +65,8 @@ _SIGS = {
     "ghom_last_error": (ctypes.c_char_p, [_vp]),
     "ghom_set_material_neohookean": (_i, [_vp, _vp, _i, _vp, _vp]),
     "ghom_set_material_svk": (_i, [_vp, _vp, _i, _vp]),
+    "ghom_set_material_visco": (_i, [_vp, _vp, _i, _vp, _vp, _vp]),
+    "ghom_set_time_step": (_i, [_vp, _d]),
     "ghom_set_stiffness_scale": (_i, [_vp, _vp]),
     "ghom_set_control": (_i, [_vp, _vp]),
     "ghom_set_history": (_i, [_vp, _i, _vp]),
@@ -198,6 +200,18 @@ class Solver:
         C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, 81)
         self._check(lib().ghom_set_material_svk(self._c, _ptr(ph), C.shape[0], _ptr(C)))
 
+    def set_material_visco(self, phase, Cinf, C1, tau):
+        ph = np.ascontiguousarray(np.asarray(phase).reshape(-1), dtype=np.uint16)
+        Ci = np.ascontiguousarray(Cinf, dtype=np.float64).reshape(-1, 81)
+        C1 = np.ascontiguousarray(C1, dtype=np.float64).reshape(-1, 81)
+        tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(-1)
+        if not (Ci.shape[0] == C1.shape[0] == tau.shape[0]):
+            raise ValueError("Cinf, C1 and tau need one entry per phase")
+        self._check(lib().ghom_set_material_visco(self._c, _ptr(ph), Ci.shape[0], _ptr(Ci), _ptr(C1), _ptr(tau)))
+
+    def set_time_step(self, dt):
+        self._check(lib().ghom_set_time_step(self._c, float(dt)))
+
     def set_stiffness_scale(self, s):
         if s is None:
             self._check(lib().ghom_set_stiffness_scale(self._c, None))
@@ -222,8 +236,12 @@ class Solver:
         """Applies a workload dict of paper_1901_06531_amd.synth."""
         if w["kind"] == "nh":
             self.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+        elif w["kind"] == "visco":
+            self.set_material_visco(w["phase"], w["Cinf"], w["C1"], w["tau"])
         else:
             self.set_material_svk(w["phase"], w["C"])
+        if w.get("dt") is not None:
+            self.set_time_step(w["dt"])
         if w.get("scale") is not None:
             self.set_stiffness_scale(w["scale"])
         self.set_control(w["mask"])
