@@ -319,6 +319,7 @@ class Oracle:
         self.tau_tab = np.asarray(tau, dtype=float).reshape(-1)
         self.E_n = np.zeros((self.N, 3, 3))
         self.Q_n = np.zeros((self.N, 3, 3))
+        self.checkpoints = []  # per increment: F at convergence, E_n, Q_n before the commit
 
     def set_time_step(self, dt):
         """Length of every load increment (rate-dependent laws only)."""
@@ -468,6 +469,7 @@ class Oracle:
         rec = self.newton(Pbar)
         self.k = k
         if self.kind == "visco":
+            self.checkpoints.append((self.F.copy(), self.E_n.copy(), self.Q_n.copy(), self.dt))
             self.commit()
         self.history.append(rec)
         return rec
@@ -526,6 +528,60 @@ class Oracle:
         return StepRecord(Favg, Pavg, newton, cg_total, per, crit)
 
     # ---- adjoint ---------------------------------------------------------------------
+    def adjoint_grad_scale_history(self, a9) -> np.ndarray:
+        """Gradient of J = a : <F> at the end of the history with respect to s(x), for the
+        viscoelastic law (a backward sweep over the checkpointed increments).
+
+        Increment n solves G*(P_n - P-bar_n) = 0 with P_n = F_n S_n,
+        S_n = s Cinf:E_n + a Q_{n-1} + b s C1:(E_n - E_{n-1}), then commits E_n = E(F_n),
+        Q_n = a Q_{n-1} + b s C1:(E_n - E_{n-1}).  Linearising in s and eliminating each
+        increment's correction with an adjoint field lam_n (A_n lam_n = G*(h_n), A_n the
+        increment's operator, symmetric on the range of G*), with L_n = sym(F_n^T lam_n):
+          h_n = F_n (mE + b s C1:mQ)  (+ a/N uniform at the last increment),
+          dJ/ds += b mQ:C1:(E_n - E_{n-1}) - L_n:(Cinf:E_n + b C1:(E_n - E_{n-1})),
+          mQ <- a (mQ - L_n),  mE <- b s C1:(L_n - mQ)  (mQ, mE start at zero),
+        from the last increment back to the first.  With C1 = 0 it reduces to
+        adjoint_grad_scale (-lam : P / s).
+        """
+        if self.kind != "visco":
+            raise OracleError("the history adjoint is for the viscoelastic law")
+        if len(self.checkpoints) != self.k or self.k == 0:
+            raise OracleError("the history adjoint needs every increment since the start")
+        keep = (self.F, self.E_n, self.Q_n, self.dt)
+        ph = self.phase
+        s = self.scale
+        Cinf = self.Cinf_tab[ph]
+        C1 = self.C1_tab[ph]
+        mQ = np.zeros((self.N, 3, 3))
+        mE = np.zeros((self.N, 3, 3))
+        grad = np.zeros(self.N)
+        abar = np.broadcast_to(np.asarray(a9, float).reshape(9, 1, 1, 1) / self.N, (9,) + self.shape)
+        try:
+            for n in range(self.k, 0, -1):
+                F9, E_prev, Q_prev, dt = self.checkpoints[n - 1]
+                self.F, self.E_n, self.Q_n, self.dt = F9, E_prev, Q_prev, dt
+                a, b = visco_factors(dt, self.tau_tab[ph])
+                Fv = _voxels(F9)
+                E = _green_lagrange(Fv)
+                C1mQ = np.einsum("nijkl,nkl->nij", C1, mQ)
+                M = mE + (b * s)[:, None, None] * C1mQ
+                h = _field(Fv @ M, self.shape)
+                if n == self.k:
+                    h = h + abar
+                lam, _ = self.conjugate_gradient(apply_projection(np.ascontiguousarray(h), self.mask, self.lengths))
+                lv = _voxels(lam)
+                FtL = Fv.transpose(0, 2, 1) @ lv
+                L = 0.5 * (FtL + FtL.transpose(0, 2, 1))
+                dE = E - E_prev
+                C1dE = np.einsum("nijkl,nkl->nij", C1, dE)
+                T = np.einsum("nijkl,nkl->nij", Cinf, E) + b[:, None, None] * C1dE
+                grad += b * np.einsum("nij,nij->n", mQ, C1dE) - np.einsum("nij,nij->n", L, T)
+                mE = (b * s)[:, None, None] * np.einsum("nijkl,nkl->nij", C1, L - mQ)
+                mQ = a[:, None, None] * (mQ - L)
+        finally:
+            self.F, self.E_n, self.Q_n, self.dt = keep
+        return grad.reshape(self.shape)
+
     def adjoint_grad_scale(self, a9) -> np.ndarray:
         """Gradient of J = a : <F> with respect to the per-voxel stiffness scale s(x).
 

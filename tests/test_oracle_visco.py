@@ -146,3 +146,77 @@ def test_hill_mandel_along_relaxation_and_creep_to_the_relaxed_state():
     C_last = last.F_avg.reshape(3, 3).T @ last.F_avg.reshape(3, 3)
     C_ref = ref.F_avg.reshape(3, 3).T @ ref.F_avg.reshape(3, 3)
     np.testing.assert_allclose(C_last, C_ref, rtol=0, atol=1e-9)
+
+
+def _visco_oracle(shape, phase, Cinf, C1, tau, mask, target, s=None, dt=0.5):
+    o = go.Oracle(shape)
+    o.set_material_visco(phase, Cinf, C1, tau)
+    o.set_time_step(dt)
+    if s is not None:
+        o.set_stiffness_scale(s)
+    o.set_control(mask)
+    o.set_history(target)
+    o.set_tolerances(1e-13, 1e-14)
+    go.run_history(o)
+    return o
+
+
+def _adjoint_case(seed=7):
+    shape = (6, 6, 6)
+    phase = _two_phase(shape, seed=seed)
+    Cinf = np.stack([_iso(1.0, 2.0), _iso(6.0, 8.0)])
+    C1 = np.stack([_iso(1.5, 1.0), _iso(3.0, 2.0)])
+    tau = [0.4, 1.5]
+    mask = synth.mask_uniaxial(0)
+    F_end = np.eye(3)
+    F_end[0, 0] = 1.04
+    ramp = synth.history_mixed(mask, F_end.reshape(9), 2)
+    target = np.concatenate([ramp, ramp[-1:], ramp[-1:]])
+    s = synth.smooth_scale_field(shape, 9, ell=0.3, lo=1.0, hi=2.0).reshape(-1)
+    a = np.zeros(9)
+    a[4] = 1.0   # <F>_22 and <F>_33 are free under this control
+    a[8] = 0.5
+    return shape, phase, Cinf, C1, tau, mask, target, s, a
+
+
+def test_history_adjoint_matches_finite_differences():
+    shape, phase, Cinf, C1, tau, mask, target, s, a = _adjoint_case()
+    o = _visco_oracle(shape, phase, Cinf, C1, tau, mask, target, s)
+    grad = o.adjoint_grad_scale_history(a).reshape(-1)
+
+    def J(sv):
+        return float(_visco_oracle(shape, phase, Cinf, C1, tau, mask, target, sv).averages()[0] @ a)
+
+    g = np.random.default_rng(2)
+    for v in g.choice(s.size, 4, replace=False):
+        h = 1e-4 * s[v]
+        sp, sm = s.copy(), s.copy()
+        sp[v] += h
+        sm[v] -= h
+        fd = (J(sp) - J(sm)) / (2 * h)
+        assert abs(fd - grad[v]) <= 1e-6 * np.max(np.abs(grad)), (v, fd, grad[v])
+    d = synth.smooth_scale_field(shape, 10, ell=0.3, lo=-1.0, hi=1.0).reshape(-1)
+    eps = 1e-5
+    fd = (J(s * (1 + eps * d)) - J(s * (1 - eps * d))) / 2
+    ad = float(np.dot(grad, eps * d * s))
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+@pytest.mark.parametrize("limit", ["slow", "no_branch"])
+def test_history_adjoint_limits_match_the_hyperelastic_adjoint(limit):
+    shape, phase, Cinf, C1, tau, mask, target, s, a = _adjoint_case(seed=8)
+    if limit == "slow":
+        tau, C_el = [1e300, 1e300], Cinf + C1
+    else:
+        C1, C_el = 0.0 * C1, Cinf
+    o = _visco_oracle(shape, phase, Cinf, C1, tau, mask, target, s)
+    got = o.adjoint_grad_scale_history(a)
+    r = go.Oracle(shape)
+    r.set_material_svk(phase, C_el)
+    r.set_stiffness_scale(s)
+    r.set_control(mask)
+    r.set_history(target)
+    r.set_tolerances(1e-13, 1e-14)
+    go.run_history(r)
+    ref = r.adjoint_grad_scale(a)
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
