@@ -109,9 +109,10 @@ int ghom_set_material_svk(ghom_ctx *ctx, const uint16_t *phase, int nphase, cons
  * stiffness tensors of 81 values each, as for ghom_set_material_svk; tau (host): nphase
  * relaxation times > 0.  The internal variables start at zero; a converged (or
  * ENOTCONVERGED) increment commits them.  Resets the deformation to F = I and the increment
- * to 0.  With this law ghom_resolve and ghom_adjoint_grad_scale return GHOM_EINVAL, and
- * ghom_load_state accepts step 0 only (it also zeroes the internal variables); the batch
- * API does not take it.  The context keeps 12 more float64 planes (E_n, Q_n). */
+ * to 0.  With this law ghom_resolve returns GHOM_EINVAL, ghom_load_state accepts step 0 only
+ * (it also zeroes the internal variables), and the batch API does not take it.  The context
+ * keeps 12 more float64 planes (E_n, Q_n).  ghom_adjoint_grad_scale works through the whole
+ * history when GHOM_OPT_CHECKPOINTS was on from increment 0. */
 int ghom_set_material_visco(ghom_ctx *ctx, const uint16_t *phase, int nphase, const double *Cinf,
                             const double *C1, const double *tau);
 
@@ -184,7 +185,12 @@ int ghom_load_state(ghom_ctx *ctx, const double *F_in, int step);
 
 /* Adjoint gradient of J = a : <F> with respect to s(x) at the current (converged) state:
  * solves A lam = G*(a/N) with the same operator, then dJ/ds(x) = -lam(x) : P(x) / s(x).
- * a (host, 9 values), grad_out (host, N values). */
+ * a (host, 9 values), grad_out (host, N values).  For the viscoelastic law (path
+ * dependent) J is taken at the end of the history and the gradient runs backward over every
+ * checkpointed increment (GHOM_OPT_CHECKPOINTS from increment 0, else GHOM_ESTATE): per
+ * increment one CG solve with that increment's operator on G*(F_n (mE + b s C1 : mQ)), where
+ * (mE, mQ) carry the sensitivity of the internal variables from the later increments; the
+ * end-of-history state is restored afterwards.  Work memory: 43 x N float64. */
 int ghom_adjoint_grad_scale(ghom_ctx *ctx, const double a[9], double *grad_out);
 
 /* ---- hot-path entry points on device memory ------------------------------------- */
@@ -210,8 +216,12 @@ enum {
   GHOM_OPT_XPROJ_F64 = 1,  /* x-pass (transform along x + projection) variant, float64    */
   GHOM_OPT_XPROJ_F32 = 2,  /* the same for the float32 transforms of GHOM_FP32_SPLIT      */
   GHOM_OPT_ZSLABS = 3,     /* number of kz slabs the y and x passes are run in (>= 1)     */
-  GHOM_OPT_GRAPHS = 4      /* 1: CG iterations are captured once into HIP graphs and
+  GHOM_OPT_GRAPHS = 4,     /* 1: CG iterations are captured once into HIP graphs and
                               replayed (not while profiling is on); 0: launched one by one */
+  GHOM_OPT_CHECKPOINTS = 5 /* 1: with the viscoelastic law, keep every accepted increment's
+                              converged F and starting internal variables on the device
+                              ((9 + 12) x N float64 each), as ghom_adjoint_grad_scale needs;
+                              0: keep none (and drop those kept) */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the faster variant by timing

@@ -93,6 +93,11 @@ struct Prob {
   float* mat32 = nullptr;
   double* visc = nullptr;  // viscoelastic law: Cinf, C1, a, b per phase
   double* iv = nullptr;    // viscoelastic law: internal variables (kViscoIV x N)
+  // viscoelastic law with checkpoints on: per accepted increment, F at convergence and the
+  // internal variables it started from ((9 + kViscoIV) x N float64 each), and its length
+  std::vector<double*> ckpt;
+  std::vector<double> ckpt_dt;
+  int ckpt_k0 = -1;  // increment index of the first checkpoint (0: the history is complete)
 };
 
 struct Engine {
@@ -119,6 +124,7 @@ struct Engine {
   int max_newton = 50, max_cg = 5000;
   int zslabs = 1;
   bool graphs = false;  // replay captured HIP graphs of CG iterations (not while profiling)
+  bool checkpoints = false;  // keep per-increment states of path-dependent laws (adjoint)
   std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, first-iteration flag, iterations
   bool prof = false;
   std::map<std::string, ProfRec> prof_recs;
@@ -807,6 +813,31 @@ void set_pbar_current(Engine& e, int p) {
 }
 
 // F = I for the given problems
+void drop_checkpoints(Engine& e, int p) {
+  Prob& q = e.P[p];
+  if (q.ckpt.empty()) return;
+  sync(e);
+  for (double* b : q.ckpt) (void)hipFree(b);
+  q.ckpt.clear();
+  q.ckpt_dt.clear();
+  q.ckpt_k0 = -1;
+}
+
+// Viscoelastic law with checkpoints on: keep F at convergence and the internal variables the
+// increment started from (call before the commit), with the increment's length.
+void visco_checkpoint(Engine& e, int p, double dt_eff) {
+  Prob& q = e.P[p];
+  if (!e.checkpoints || q.kind != MAT_VISCO) return;
+  const size_t N = (size_t)e.C[q.cls].g.N;
+  double* buf = nullptr;
+  HIPCALL(hipMalloc((void**)&buf, (9 + kViscoIV) * N * sizeof(double)));
+  if (q.ckpt.empty()) q.ckpt_k0 = q.k;
+  q.ckpt.push_back(buf);
+  q.ckpt_dt.push_back(dt_eff);
+  HIPCALL(hipMemcpyAsync(buf, e.hdesc[p].F, 9 * N * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+  HIPCALL(hipMemcpyAsync(buf + 9 * N, q.iv, kViscoIV * N * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+}
+
 void reset_state(Engine& e, const std::vector<int>& set) {
   for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
   for (int p : set) {
@@ -815,6 +846,7 @@ void reset_state(Engine& e, const std::vector<int>& set) {
     Prob& q = e.P[p];
     q.k = 0;
     q.state_valid = false;
+    drop_checkpoints(e, p);
     for (int i = 0; i < 9; ++i) {
       q.Favg[i] = e.hdesc[p].fill[i];
       q.Pavg[i] = 0.0;
@@ -854,6 +886,7 @@ void destroy_engine(Engine* e) {
     if (q.mat32) (void)hipFree(q.mat32);
     if (q.visc) (void)hipFree(q.visc);
     if (q.iv) (void)hipFree(q.iv);
+    for (double* b : q.ckpt) (void)hipFree(b);
   }
   for (auto& c : e->C) {
     if (c.ids) (void)hipFree(c.ids);
@@ -1359,7 +1392,10 @@ int ghom_step(ghom_ctx* c, ghom_step_info* info) {
     begin_increment(e, {0});
     newton(e, {0});
     if (q.status == GHOM_OK || q.status == GHOM_ENOTCONVERGED) {
-      if (q.kind == MAT_VISCO) visco_commit(e, 0);
+      if (q.kind == MAT_VISCO) {
+        visco_checkpoint(e, 0, q.dt);
+        visco_commit(e, 0);
+      }
       q.k += 1;
     }
     return finish_solve(e, 0, info);
@@ -1409,7 +1445,10 @@ int ghom_step_adaptive(ghom_ctx* c, int max_cuts, int grow_below, ghom_step_info
       tot.crit = q.info.crit;
       tot.res_rms = q.info.res_rms;
       if (q.status == GHOM_OK) {
-        if (q.kind == MAT_VISCO) visco_commit(e, 0);
+        if (q.kind == MAT_VISCO) {
+          visco_checkpoint(e, 0, (clk.next_end() - clk.theta) * q.dt);
+          visco_commit(e, 0);
+        }
         clk.accept(q.info.newton_iters);
         ++subs;
         continue;
@@ -1510,6 +1549,7 @@ int ghom_load_state(ghom_ctx* c, const double* F_in, int step) {
     if (q.kind == MAT_VISCO) {
       hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, (long long)kViscoIV * e.C[q.cls].g.N, q.iv);
       HIPCALL(hipGetLastError());
+      drop_checkpoints(e, 0);
     }
     q.k = step;
     q.state_valid = false;
@@ -1518,13 +1558,129 @@ int ghom_load_state(ghom_ctx* c, const double* F_in, int step) {
   });
 }
 
+namespace {
+
+// Gradient of J = a : <F> at the end of a viscoelastic history with respect to s(x): the
+// backward sweep over the checkpointed increments.  For increment n (last to first), with
+// that increment's state (F_n, the internal variables it started from, its length) restored:
+// h = F_n (mE + b s C1 : mQ) (+ a/N at the last increment), lam solves A_n lam = G*(h) by CG
+// with the increment's operator, then the gradient and (mE, mQ) are updated from
+// L = sym(F_n^T lam) (visco_adj_update_kernel).  The state of the end of the history is
+// restored afterwards: F, the committed internal variables, and P, the tangent state and
+// the averages of the last increment's converged evaluation.
+void visco_history_adjoint(Engine& e, const double* a, double* grad_out) {
+  Prob& q = e.P[0];
+  ShapeClass& cl = e.C[q.cls];
+  const long long N = cl.g.N;
+  if (q.ckpt.empty() || q.ckpt_k0 != 0)
+    fail(GHOM_ESTATE, "the adjoint of a viscoelastic history needs checkpoints (GHOM_OPT_CHECKPOINTS) from increment 0");
+  const size_t M = q.ckpt.size();
+  refresh_averages(e, 0);
+  double Fa[9], Pa[9];
+  std::copy(q.Favg, q.Favg + 9, Fa);
+  std::copy(q.Pavg, q.Pavg + 9, Pa);
+  sync(e);
+  double* buf = nullptr;
+  const size_t nd = (size_t)(9 + kViscoIV + 1 + 9 + kViscoIV) * N + 16;
+  HIPCALL(hipMalloc((void**)&buf, nd * sizeof(double)));
+  double* h = buf;
+  double* mu = h + 9 * N;
+  double* gd = mu + kViscoIV * N;
+  double* Fkeep = gd + N;
+  double* ivkeep = Fkeep + 9 * N;
+  double* abar = ivkeep + kViscoIV * N;
+  double* F = e.hdesc[0].F;
+  const size_t fb = 9 * (size_t)N * sizeof(double), ib = kViscoIV * (size_t)N * sizeof(double);
+  bool restored = false;
+  auto restore = [&]() {
+    if (restored) return;
+    restored = true;
+    (void)hipMemcpyAsync(F, Fkeep, fb, hipMemcpyDeviceToDevice, e.stream);
+    (void)hipMemcpyAsync(q.iv, ivkeep, ib, hipMemcpyDeviceToDevice, e.stream);
+    (void)hipStreamSynchronize(e.stream);
+    (void)hipFree(buf);
+    e.hdesc[0].in = nullptr;
+    q.state_valid = false;
+  };
+  try {
+    HIPCALL(hipMemcpyAsync(Fkeep, F, fb, hipMemcpyDeviceToDevice, e.stream));
+    HIPCALL(hipMemcpyAsync(ivkeep, q.iv, ib, hipMemcpyDeviceToDevice, e.stream));
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, (long long)(kViscoIV + 1) * N, mu);
+    HIPCALL(hipGetLastError());
+    double ab[9];
+    for (int i = 0; i < 9; ++i) ab[i] = a[i] / (double)N;
+    HIPCALL(hipMemcpyAsync(abar, ab, sizeof(ab), hipMemcpyHostToDevice, e.stream));
+    const dim3 vg(cl.vb), vt(kVoxThreads);
+    const double* scale = e.hdesc[0].has_scale ? e.hdesc[0].scale : nullptr;
+    for (size_t n = M; n >= 1; --n) {
+      double* ck = q.ckpt[n - 1];
+      HIPCALL(hipMemcpyAsync(F, ck, fb, hipMemcpyDeviceToDevice, e.stream));
+      HIPCALL(hipMemcpyAsync(q.iv, ck + 9 * N, ib, hipMemcpyDeviceToDevice, e.stream));
+      visco_tables(e, 0, q.ckpt_dt[n - 1]);
+      refresh_averages(e, 0);  // P and the tangent state of increment n
+      hipLaunchKernelGGL(visco_adj_rhs_kernel, vg, vt, 0, e.stream, N, F, e.hdesc[0].phase, scale, q.visc, mu, h,
+                         n == M ? abar : nullptr);
+      HIPCALL(hipGetLastError());
+      e.hdesc[0].in = h;
+      e.hdesc[0].active = 1;
+      upload_descs(e);
+      const int gi = project64(e, cl, ROLE_ADJ, "adj");
+      hipLaunchKernelGGL(sum_columns_batch, dim3(1), dim3(kRedThreads), 0, e.stream, e.ddesc, cl.ids, gi, 1, 0, 0, 20);
+      HIPCALL(hipGetLastError());
+      HIPCALL(hipMemcpyAsync(e.host_red, e.red, 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+      sync(e);
+      const double rr = e.host_red[20];
+      const double tol = std::max(e.cg_tol, forcing(e) * std::sqrt(rr / (double)N));
+      e.hdesc[0].cg_thresh = tol * tol * (double)N;
+      e.hdesc[0].rr0 = rr;
+      e.hdesc[0].max_cg = e.max_cg;
+      upload_descs(e);
+      double tcg = 0.0;
+      if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg);
+      else cg_solve<float>(e, &tcg);
+      const CGScalars st = e.host_sc[0];
+      if (st.status == 2 && st.it == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
+      if (st.status == 3) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+      const double* lam = reinterpret_cast<const double*>(e.hdesc[0].x);
+      if (e.prec == GHOM_FP32_SPLIT) {
+        project64(e, cl, ROLE_REPROJ, "reproj");
+        lam = e.hdesc[0].dF64;
+      }
+      hipLaunchKernelGGL(visco_adj_update_kernel, vg, vt, 0, e.stream, N, F, q.iv, e.hdesc[0].phase, scale, q.visc,
+                         lam, mu, gd);
+      HIPCALL(hipGetLastError());
+    }
+    sync(e);
+    HIPCALL(hipMemcpy(grad_out, gd, (size_t)N * sizeof(double), hipMemcpyDeviceToHost));
+    // the last increment's converged evaluation (its starting internal variables and length),
+    // then the committed internal variables
+    HIPCALL(hipMemcpyAsync(F, Fkeep, fb, hipMemcpyDeviceToDevice, e.stream));
+    HIPCALL(hipMemcpyAsync(q.iv, q.ckpt[M - 1] + 9 * N, ib, hipMemcpyDeviceToDevice, e.stream));
+    visco_tables(e, 0, q.ckpt_dt[M - 1]);
+    refresh_averages(e, 0);
+  } catch (...) {
+    restore();
+    visco_tables(e, 0, q.dt);
+    throw;
+  }
+  restore();
+  q.state_valid = true;
+  std::copy(Fa, Fa + 9, q.Favg);
+  std::copy(Pa, Pa + 9, q.Pavg);
+}
+
+}  // namespace
+
 int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
   return guard(c, [&]() -> int {
     Engine& e = *c->e;
     Prob& q = e.P[0];
     check_material(q);
     if (!a || !grad_out) fail(GHOM_EINVAL, "null argument");
-    if (q.kind == MAT_VISCO) fail(GHOM_EINVAL, "the adjoint is for path-independent (hyperelastic) laws");
+    if (q.kind == MAT_VISCO) {
+      visco_history_adjoint(e, a, grad_out);
+      return GHOM_OK;
+    }
     const long long N = e.C[q.cls].g.N;
     // right-hand side G*(a) of a uniform a: only xi = 0 content, kept on the
     // stress-controlled components (the 1/N of G*(a/N) is applied to the solution)
@@ -1655,6 +1811,13 @@ static int set_option(Engine& e, int key, int value) {
     drop_graphs(e);
     return GHOM_OK;
   }
+  if (key == GHOM_OPT_CHECKPOINTS) {
+    if (value != 0 && value != 1) fail(GHOM_EINVAL, "checkpoint option must be 0 or 1");
+    e.checkpoints = value != 0;
+    if (!e.checkpoints)
+      for (size_t p = 0; p < e.P.size(); ++p) drop_checkpoints(e, (int)p);
+    return GHOM_OK;
+  }
   if (key == GHOM_OPT_GRAPHS) {
     if (value != 0 && value != 1) fail(GHOM_EINVAL, "graph option must be 0 or 1");
     e.graphs = value != 0;
@@ -1670,6 +1833,7 @@ static int get_option(Engine& e, int key, int* value) {
   else if (key == GHOM_OPT_XPROJ_F32) *value = e.C[0].xproj_var[1];
   else if (key == GHOM_OPT_ZSLABS) *value = e.zslabs;
   else if (key == GHOM_OPT_GRAPHS) *value = e.graphs ? 1 : 0;
+  else if (key == GHOM_OPT_CHECKPOINTS) *value = e.checkpoints ? 1 : 0;
   else fail(GHOM_EINVAL, "unknown option");
   return GHOM_OK;
 }

@@ -1143,7 +1143,8 @@ enum {
   ROLE_RESID = 2,     // -G*(P - P-bar) into b, with b.b partials
   ROLE_REPROJ = 3,    // G*(x) into dF64 (float64)
   ROLE_PROJ = 4,      // G*(in) into out (float64)
-  ROLE_NEWTON = 5     // F += G*(x) (float64) with the Newton-update partials
+  ROLE_NEWTON = 5,    // F += G*(x) (float64) with the Newton-update partials
+  ROLE_ADJ = 6        // G*(in) into b (float64) with b.b partials: an adjoint right-hand side
 };
 
 struct ProbDesc {
@@ -1277,9 +1278,10 @@ zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
     a.F = d.F;
     a.pstride = (int)gridDim.x;
   } else {
-    a.out = role == ROLE_RESID ? reinterpret_cast<TOUT*>(d.b)
-                               : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
-    a.dot_with = role == ROLE_RESID ? a.out : nullptr;
+    a.out = (role == ROLE_RESID || role == ROLE_ADJ)
+                ? reinterpret_cast<TOUT*>(d.b)
+                : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
+    a.dot_with = (role == ROLE_RESID || role == ROLE_ADJ) ? a.out : nullptr;
   }
   zinv_body<T, A, B, TOUT, ZM>(d.g, a, blockIdx.x);
 }
@@ -1403,6 +1405,105 @@ adjoint_grad_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) 
   const double* lam = d.dF64 ? d.dF64 : reinterpret_cast<const double*>(d.x);
   adjoint_grad_body<double>(d.g.N, lam, d.P, d.has_scale ? d.scale : nullptr, 1.0 / (double)d.g.N,
                             reinterpret_cast<double*>(d.out), blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------------
+// Adjoint through a viscoelastic history (one problem; the backward sweep of the history
+// adjoint).  Symmetric tensors are 6 tensor components (11 22 33 23 13 12); contractions
+// carry the weights (1, 1, 1, 2, 2, 2); the Voigt tables act on engineering strains.
+// mu holds mE (6 planes) then mQ (6 planes).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double voigt_w(int I) { return I < 3 ? 1.0 : 2.0; }
+
+// h = F (mE + b s C1 : mQ), plus the uniform abar when given (the last increment)
+__global__ void __launch_bounds__(kVoxThreads)
+visco_adj_rhs_kernel(long long N, const double* __restrict__ F, const uint16_t* __restrict__ phase,
+                     const double* __restrict__ scale, const double* __restrict__ visc, const double* __restrict__ mu,
+                     double* __restrict__ h, const double* __restrict__ abar) {
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+    const double* t = visc + kViscoTable * phase[v];
+    const double bs = t[73] * (scale ? scale[v] : 1.0);
+    double M[6];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      double c = 0.0;
+#pragma unroll
+      for (int J = 0; J < 6; ++J) c += t[36 + 6 * I + J] * voigt_w(J) * mu[(6 + J) * N + v];
+      M[I] = mu[I * N + v] + bs * c;
+    }
+    const double Mm[9] = {M[0], M[5], M[4], M[5], M[1], M[3], M[4], M[3], M[2]};
+    double f[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) f[c] = F[c * N + v];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double acc = abar ? abar[3 * i + j] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc += f[3 * i + k] * Mm[3 * k + j];
+        h[(3 * i + j) * N + v] = acc;
+      }
+  }
+}
+
+// With L = sym(F^T lam): grad += b mQ : C1 : (E - E_prev) - L : (Cinf : E + b C1 : (E - E_prev)),
+// mE <- b s C1 : (L - mQ), mQ <- a (mQ - L).  E from F; E_prev from iv (engineering shears).
+__global__ void __launch_bounds__(kVoxThreads)
+visco_adj_update_kernel(long long N, const double* __restrict__ F, const double* __restrict__ iv,
+                        const uint16_t* __restrict__ phase, const double* __restrict__ scale,
+                        const double* __restrict__ visc, const double* __restrict__ lam, double* __restrict__ mu,
+                        double* __restrict__ grad) {
+  for (long long v = (long long)blockIdx.x * kVoxThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kVoxThreads) {
+    const double* t = visc + kViscoTable * phase[v];
+    const double a = t[72], b = t[73];
+    const double s = scale ? scale[v] : 1.0;
+    double f[9], l[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      f[c] = F[c * N + v];
+      l[c] = lam[c * N + v];
+    }
+    // (F^T lam)_ij = sum_k F_ki lam_kj
+    auto ftl = [&](int i, int j) { return f[i] * l[j] + f[3 + i] * l[3 + j] + f[6 + i] * l[6 + j]; };
+    double L[6];
+    L[0] = ftl(0, 0);
+    L[1] = ftl(1, 1);
+    L[2] = ftl(2, 2);
+    L[3] = 0.5 * (ftl(1, 2) + ftl(2, 1));
+    L[4] = 0.5 * (ftl(0, 2) + ftl(2, 0));
+    L[5] = 0.5 * (ftl(0, 1) + ftl(1, 0));
+    auto ftf = [&](int i, int j) { return f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j]; };
+    double E[6];
+    E[0] = 0.5 * (ftf(0, 0) - 1.0);
+    E[1] = 0.5 * (ftf(1, 1) - 1.0);
+    E[2] = 0.5 * (ftf(2, 2) - 1.0);
+    E[3] = ftf(1, 2);
+    E[4] = ftf(0, 2);
+    E[5] = ftf(0, 1);
+    double mQ[6], dE[6];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      mQ[I] = mu[(6 + I) * N + v];
+      dE[I] = E[I] - iv[I * N + v];
+    }
+    double g = 0.0;
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      double c1 = 0.0, ci = 0.0, cl = 0.0;
+#pragma unroll
+      for (int J = 0; J < 6; ++J) {
+        c1 += t[36 + 6 * I + J] * dE[J];
+        ci += t[6 * I + J] * E[J];
+        cl += t[36 + 6 * I + J] * voigt_w(J) * (L[J] - mQ[J]);
+      }
+      g += voigt_w(I) * (b * mQ[I] * c1 - L[I] * (ci + b * c1));
+      mu[I * N + v] = b * s * cl;
+    }
+#pragma unroll
+    for (int I = 0; I < 6; ++I) mu[(6 + I) * N + v] = a * (mQ[I] - L[I]);
+    grad[v] += g;
+  }
 }
 
 }  // namespace ghom

@@ -1,8 +1,9 @@
 """The viscoelastic law (path- and rate-dependent, internal variables) on the GPU against the
 oracle: increment by increment under mixed control (a stretch ramp, then a hold in which the
 stress relaxes) and under prescribed normal stresses (a stress ramp, then creep), in FP64 and in
-the FP32-split precision; the operator at a relaxed state; and the calls that a path-dependent
-law refuses."""
+the FP32-split precision; the operator at a relaxed state; the adjoint through the whole
+history (backward sweep over checkpointed increments) against the oracle's and against finite
+differences; and the calls that a path-dependent law refuses."""
 
 import numpy as np
 import pytest
@@ -102,12 +103,84 @@ def test_visco_refusals():
     with ghom.Solver(w["shape"]) as s:
         s.setup(w)
         s.step()
-        for call in (lambda: s.resolve(), lambda: s.adjoint_grad_scale(np.eye(3).reshape(9)),
-                     lambda: s.load_state(s.save_state()[0], 1), lambda: s.set_time_step(0.0)):
+        for call in (lambda: s.resolve(), lambda: s.load_state(s.save_state()[0], 1), lambda: s.set_time_step(0.0)):
             with pytest.raises(ghom.GhomError) as e:
                 call()
             assert e.value.name == "EINVAL"
+        with pytest.raises(ghom.GhomError) as e:  # no checkpoints were kept
+            s.adjoint_grad_scale(np.eye(3).reshape(9))
+        assert e.value.name == "ESTATE"
         F0 = np.broadcast_to(np.eye(3).reshape(9, 1, 1, 1), (9,) + w["shape"])
         s.load_state(F0, 0)  # restart: the internal variables return to zero
         info = s.step()
         assert info["status"] == 0
+
+
+def _adjoint_workload(shape):
+    w = _workload(shape, "mixed")
+    w["scale"] = synth.smooth_scale_field(shape, 9, ell=0.3, lo=1.0, hi=2.0)
+    w["target"] = w["target"][:5]
+    return w
+
+
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_visco_history_adjoint_matches_oracle(prec):
+    w = _adjoint_workload((12, 16, 8))
+    a = np.zeros(9)
+    a[4] = 1.0
+    a[8] = 0.5
+    o = go.Oracle(w["shape"])
+    o.set_material_visco(w["phase"], w["Cinf"], w["C1"], w["tau"])
+    o.set_time_step(w["dt"])
+    o.set_stiffness_scale(w["scale"])
+    o.set_control(w["mask"])
+    o.set_history(w["target"])
+    o.set_tolerances(1e-12, 1e-13)
+    go.run_history(o)
+    ref = o.adjoint_grad_scale_history(a)
+    with ghom.Solver(w["shape"], precision=prec) as s:
+        s.setup(w)
+        s.set_tolerances(1e-12, 1e-13, 1e-5 if prec == ghom.FP32_SPLIT else 0.0)
+        s.set_option(ghom.OPT_CHECKPOINTS, 1)
+        for _ in range(len(w["target"])):
+            s.step()
+        F_end, P_end = s.averages()
+        got = s.adjoint_grad_scale(a)
+        F_after, P_after = s.averages()
+        np.testing.assert_array_equal(F_after, F_end)  # the end state is back
+        np.testing.assert_allclose(P_after, P_end, rtol=0, atol=1e-14)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say("history adjoint vs oracle: %.3e" % err)
+    # FP32-split stops each of the 5 adjoint CG solves at 1e-5 of its right-hand side (the
+    # split mode's forcing floor); every increment adds an error of that order: 5 x 1e-5 x 2
+    assert err < (1e-9 if prec == ghom.FP64 else 1e-4)
+
+
+def test_visco_history_adjoint_matches_finite_differences_32():
+    w = _adjoint_workload((32, 32, 32))
+    a = np.zeros(9)
+    a[4] = 1.0
+    s0 = w["scale"].reshape(-1)
+    d = synth.smooth_scale_field(w["shape"], 10, ell=0.2, lo=-1.0, hi=1.0).reshape(-1)
+    eps = 1e-5
+    with ghom.Solver(w["shape"]) as s:
+        s.setup(w)
+        s.set_tolerances(1e-12, 1e-13)
+        s.set_option(ghom.OPT_CHECKPOINTS, 1)
+        for _ in range(len(w["target"])):
+            s.step()
+        grad = s.adjoint_grad_scale(a).reshape(-1)
+        s.set_option(ghom.OPT_CHECKPOINTS, 0)
+        F0 = np.broadcast_to(np.eye(3).reshape(9, 1, 1, 1), (9,) + w["shape"])
+
+        def J(sv):
+            s.set_stiffness_scale(sv)
+            s.load_state(F0, 0)
+            for _ in range(len(w["target"])):
+                s.step()
+            return float(s.averages()[0] @ a)
+
+        fd = (J(s0 * (1 + eps * d)) - J(s0 * (1 - eps * d))) / 2
+    ad = float(np.dot(grad, eps * d * s0))
+    say("directional: fd %.8e adjoint %.8e" % (fd, ad))
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
