@@ -45,3 +45,22 @@ def test_argument_checks_need_no_gpu():
     assert L.ghom_create(ctypes.byref(out), 16, 16, 16, -1.0, 1.0, 1.0, 0, 0, None) == -1
     assert L.ghom_create(None, 16, 16, 16, 1.0, 1.0, 1.0, 0, 0, None) == -1
     assert L.ghom_set_control(None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(ghom.LIB_PATH), reason="libghom.so not built")
+def test_new_entry_points_reject_null_contexts():
+    L = ghom.lib()
+    assert L.ghom_set_time_step(None, 1.0) == -1
+    assert L.ghom_set_material_visco(None, None, 1, None, None, None) == -1
+    assert L.ghom_step_adaptive(None, 4, 2, None, None, None) == -1
+    assert L.ghom_set_option(None, 4, 1) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No CPU fallback: without the built library every call raises."""
+    monkeypatch.setattr(ghom, "LIB_PATH", "/nonexistent/libghom.so")
+    monkeypatch.setattr(ghom, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        ghom.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        ghom.Solver((16, 16, 16))

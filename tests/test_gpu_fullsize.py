@@ -206,3 +206,69 @@ def test_full_batch_increment_matches_single_solves_and_oracle_equilibrium():
             mask = np.asarray(w["mask"]) > 0
             np.testing.assert_allclose(Fb[~mask], w["target"][0][~mask], rtol=0, atol=1e-14)
             np.testing.assert_allclose(Pb[mask], Pbar[mask], rtol=0, atol=1e-6)
+
+
+def test_projection_properties_at_512():
+    """The largest supported grid (512^3), FP64: G* is idempotent and self-adjoint, its
+    output has zero mean on deformation-controlled components and keeps the stress-controlled
+    ones; a gradient plane wave a (x) xi at a wave number off the Nyquist set is kept unchanged
+    and a wave whose rows are orthogonal to xi is removed (the closed form of eq. 9)."""
+    shape = (512, 512, 512)
+    mask = synth.mask_uniaxial(0)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    w = dict(shape=shape, kind="nh", phase=np.zeros(shape, np.uint16), mu=[1.0], lam=[2.0], mask=mask,
+             target=np.zeros((1, 9)), newton_tol=1e-6, cg_tol=1e-8)
+    with ghom.Solver(shape) as s:
+        s.setup(w)
+        say("projections at 512^3")
+        u = torch.randn((9,) + shape, dtype=torch.float64, device="cuda", generator=g)
+        v = torch.randn((9,) + shape, dtype=torch.float64, device="cuda", generator=g)
+        Gu = s.apply_projection(u)
+        GGu = s.apply_projection(Gu)
+        assert float((GGu - Gu).abs().max()) < 1e-12 * float(Gu.abs().max())
+        del GGu
+        Gv = s.apply_projection(v)
+        lhs = float(torch.sum(Gu * v))
+        rhs = float(torch.sum(u * Gv))
+        assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+        means = Gu.reshape(9, -1).mean(dim=1).cpu().numpy()
+        umeans = u.reshape(9, -1).mean(dim=1).cpu().numpy()
+        fm = np.asarray(mask) == 0
+        assert np.max(np.abs(means[fm])) < 1e-15
+        np.testing.assert_allclose(means[~fm], umeans[~fm], rtol=0, atol=1e-13)
+        del u, v, Gu, Gv
+        # plane waves: A(x) = Re(M exp(2 pi i k.x)) with M = a (x) xi (compatible) or M xi = 0
+        k = np.array([3, -5, 7])
+        xs = [torch.arange(n, dtype=torch.float64, device="cuda") / n for n in shape]
+        phase = 2 * np.pi * (k[0] * xs[0][:, None, None] + k[1] * xs[1][None, :, None] + k[2] * xs[2][None, None, :])
+        c = torch.cos(phase)
+        xi = k.astype(float)
+        a = np.array([0.3, -1.1, 0.7])
+        Mc = np.outer(a, xi)
+        Mo = np.outer(a, np.cross(xi, [1.0, 2.0, 3.0]))  # every row orthogonal to xi
+        for M, keep in ((Mc, True), (Mo, False)):
+            f = torch.stack([float(M.reshape(9)[i]) * c for i in range(9)])
+            out = s.apply_projection(f)
+            ref = f if keep else torch.zeros_like(f)
+            assert float((out - ref).abs().max()) < 1e-11 * float(f.abs().max())
+            del f, out, ref
+    torch.cuda.empty_cache()
+
+
+def test_homogeneous_256_strain_control_needs_no_cg():
+    """A homogeneous cell under full strain control is in equilibrium with a uniform field:
+    one Newton check, no CG iteration, <P> = P(F-bar) (a degenerate case of the method)."""
+    shape = (256, 256, 256)
+    F_end = np.array([[1.02, 0.01, 0.0], [0.0, 0.99, 0.003], [0.0, 0.0, 1.005]])
+    w = dict(shape=shape, kind="nh", phase=np.zeros(shape, np.uint16), mu=[1.0], lam=[2.0],
+             mask=synth.mask_full_strain(), target=synth.history_strain_ramp(F_end.reshape(9), 1),
+             newton_tol=1e-10, cg_tol=1e-12)
+    Pref = go.nh_stress(F_end[None], np.array([1.0]), np.array([2.0]))[0].reshape(9)
+    for prec in (ghom.FP64, ghom.FP32_SPLIT):
+        with ghom.Solver(shape, precision=prec) as s:
+            s.setup(w)
+            info = s.step()
+            assert info["newton_iters"] == 1 and info["cg_iters_total"] == 0
+            F, P = s.averages()
+            np.testing.assert_allclose(F, F_end.reshape(9), rtol=0, atol=1e-15)
+            np.testing.assert_allclose(P, Pref, rtol=0, atol=1e-14)
