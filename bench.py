@@ -80,10 +80,21 @@ def run_gpu(w, precision, steps, warmup, profile):
     # both precisions stop CG at max(1e-8, 1e-5 |b|): the float32 CG needs the relative
     # floor, and the float64 run uses the same rule so that the two are compared fairly
     s.set_tolerances(w["newton_tol"], w["cg_tol"], CG_FORCING)
+    # warm-up: every launch timed, to find the operator pass with the largest share; the
+    # timed region then brackets only that kernel with events (each timed launch costs a
+    # few microseconds)
+    if profile and warmup:
+        s.profile_reset()
+        s.set_profiling(True)
     for i in range(warmup):
         info = s.step()
         log("  warmup increment %d: newton %d cg %d  %.1f ms" % (i + 1, info["newton_iters"], info["cg_iters_total"],
                                                                  info["t_total_ms"]))
+    warm_prof = {}
+    if profile and warmup:
+        warm_prof = s.profile()
+        op = {k: v for k, v in warm_prof.items() if k.startswith("op_")}
+        s.set_profiling_filter(max(op, key=lambda k: op[k][1]) if op else None)
     import torch
     torch.cuda.synchronize()
     if profile:
@@ -101,6 +112,9 @@ def run_gpu(w, precision, steps, warmup, profile):
     prof = s.profile() if profile else {}
     F, P = s.averages()
     s.close()
+    if warm_prof:
+        log("kernel times (warm-up, every launch timed): " + ", ".join(
+            "%s %.3f ms x%d" % (k, v[1] / v[0], v[0]) for k, v in sorted(warm_prof.items()) if k.startswith("op_")))
     cg = sum(i["cg_iters_total"] for i in infos)
     newton = sum(i["newton_iters"] for i in infos)
     N = int(np.prod(w["shape"]))

@@ -243,6 +243,11 @@ int ghom_get_option(ghom_ctx *ctx, int key, int *value);
 /* Enables (1) or disables (0) HIP-event timing of every kernel launch of the context. */
 int ghom_set_profiling(ghom_ctx *ctx, int on);
 
+/* Restricts the timing to launches whose record name is exactly `name` (host string,
+ * copied; NULL or "" times every launch again).  Each timed launch is bracketed by two
+ * events on the context's stream, which costs a few microseconds per launch. */
+int ghom_set_profiling_filter(ghom_ctx *ctx, const char *name);
+
 /* Kernel timing records: number of distinct kernel names seen since profiling started. */
 int ghom_profile_count(ghom_ctx *ctx);
 

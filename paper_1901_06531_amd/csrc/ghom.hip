@@ -127,6 +127,7 @@ struct Engine {
   bool checkpoints = false;  // keep per-increment states of path-dependent laws (adjoint)
   std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, first-iteration flag, iterations
   bool prof = false;
+  std::string prof_only;  // time only launches of this name (empty: all)
   std::map<std::string, ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   std::string err;
@@ -168,7 +169,7 @@ hipEvent_t get_event(Engine& e) {
 // Runs `launch` on the engine stream, bracketed by events when profiling.
 template <typename L>
 void timed(Engine& e, const std::string& name, L&& launch) {
-  if (!e.prof) {
+  if (!e.prof || (!e.prof_only.empty() && name != e.prof_only)) {
     launch();
     HIPCALL(hipGetLastError());
     return;
@@ -1849,6 +1850,13 @@ int ghom_get_option(ghom_ctx* c, int key, int* value) {
 int ghom_set_profiling(ghom_ctx* c, int on) {
   return guard(c, [&]() -> int {
     c->e->prof = on != 0;
+    return GHOM_OK;
+  });
+}
+
+int ghom_set_profiling_filter(ghom_ctx* c, const char* name) {
+  return guard(c, [&]() -> int {
+    c->e->prof_only = name ? std::string(name) : std::string();
     return GHOM_OK;
   });
 }

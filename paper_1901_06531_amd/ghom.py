@@ -96,6 +96,7 @@ _SIGS = {
     "ghom_set_option": (_i, [_vp, _i, _i]),
     "ghom_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
     "ghom_set_profiling": (_i, [_vp, _i]),
+    "ghom_set_profiling_filter": (_i, [_vp, ctypes.c_char_p]),
     "ghom_profile_count": (_i, [_vp]),
     "ghom_profile_get": (_i, [_vp, _i, ctypes.c_char_p, _i, ctypes.POINTER(_i), _dp]),
     "ghom_profile_reset": (_i, [_vp]),
@@ -341,6 +342,10 @@ class Solver:
     # -- profiling -----------------------------------------------------------------------
     def set_profiling(self, on=True):
         self._check(lib().ghom_set_profiling(self._c, int(bool(on))))
+
+    def set_profiling_filter(self, name=None):
+        """Time only the launches recorded under `name` (None: all)."""
+        self._check(lib().ghom_set_profiling_filter(self._c, None if name is None else name.encode()))
 
     def profile(self):
         n = lib().ghom_profile_count(self._c)
