@@ -83,7 +83,8 @@ int ghom_create(ghom_ctx **out, int nx, int ny, int nz, double Lx, double Ly, do
 /* Releases the context and all its device memory (NULL is ignored). */
 void ghom_destroy(ghom_ctx *ctx);
 
-/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+/* Message of the last failed call on ctx ("" if none); valid until the next call.  With
+ * ctx NULL: the reason the last ghom_create or ghom_batch_create of this thread failed. */
 const char *ghom_last_error(const ghom_ctx *ctx);
 
 /* Compressible neo-Hookean phases: W = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,

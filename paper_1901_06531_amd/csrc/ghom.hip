@@ -1224,15 +1224,27 @@ void open_stream(Engine& e, void* hip_stream) {
 
 extern "C" {
 
+namespace {
+// message of the last failed ghom_create / ghom_batch_create of this thread
+thread_local std::string g_create_err;
+int create_fail(int code, const std::string& msg) {
+  g_create_err = msg;
+  return code;
+}
+const char* kLengths = "4, 6, 8, 9, 12, 16, 18, 24, 27, 32, 36, 48, 64, 72, 96, 128, 144, 192, 256, 512";
+}  // namespace
+
 int ghom_create(ghom_ctx** out, int nx, int ny, int nz, double Lx, double Ly, double Lz, int precision, int device,
                 void* hip_stream) {
-  if (!out) return GHOM_EINVAL;
+  g_create_err.clear();
+  if (!out) return create_fail(GHOM_EINVAL, "null output");
   *out = nullptr;
-  if (!supported_length(nx) || !supported_length(ny) || !supported_length(nz)) return GHOM_EINVAL;
-  if (!(Lx > 0 && Ly > 0 && Lz > 0)) return GHOM_EINVAL;
-  if (precision != GHOM_FP64 && precision != GHOM_FP32_SPLIT) return GHOM_EINVAL;
+  if (!supported_length(nx) || !supported_length(ny) || !supported_length(nz))
+    return create_fail(GHOM_EINVAL, std::string("grid lengths must be among ") + kLengths);
+  if (!(Lx > 0 && Ly > 0 && Lz > 0)) return create_fail(GHOM_EINVAL, "cell lengths must be > 0");
+  if (precision != GHOM_FP64 && precision != GHOM_FP32_SPLIT) return create_fail(GHOM_EINVAL, "unknown precision");
   Engine* e = new_engine(precision, device, hip_stream);
-  if (!e) return GHOM_ENOMEM;
+  if (!e) return create_fail(GHOM_ENOMEM, "host allocation failed");
   const int rc = guarded(e, [&]() -> int {
     open_stream(*e, hip_stream);
     build_engine(*e, {ProbSpec{nx, ny, nz, {Lx, Ly, Lz}}}, {0});
@@ -1240,6 +1252,7 @@ int ghom_create(ghom_ctx** out, int nx, int ny, int nz, double Lx, double Ly, do
   });
   ghom_ctx* c = rc == GHOM_OK ? new (std::nothrow) ghom_ctx() : nullptr;
   if (!c) {
+    g_create_err = rc != GHOM_OK ? e->err : std::string("host allocation failed");
     destroy_engine(e);
     return rc != GHOM_OK ? rc : GHOM_ENOMEM;
   }
@@ -1254,7 +1267,10 @@ void ghom_destroy(ghom_ctx* c) {
   delete c;
 }
 
-const char* ghom_last_error(const ghom_ctx* c) { return c && c->e ? c->e->err.c_str() : "null context"; }
+const char* ghom_last_error(const ghom_ctx* c) {
+  if (!c) return g_create_err.empty() ? "null context" : g_create_err.c_str();
+  return c->e ? c->e->err.c_str() : "null context";
+}
 
 int ghom_set_material_neohookean(ghom_ctx* c, const uint16_t* phase, int nphase, const double* mu,
                                  const double* lambda) {
@@ -1896,26 +1912,30 @@ int ghom_profile_reset(ghom_ctx* c) {
 // =====================================================================================
 int ghom_batch_create(ghom_batch** out, const ghom_problem* probs, int nprob, int precision, int device,
                       void* hip_stream) {
-  if (!out) return GHOM_EINVAL;
+  g_create_err.clear();
+  if (!out) return create_fail(GHOM_EINVAL, "null output");
   *out = nullptr;
-  if (!probs || nprob < 1 || nprob > 65535) return GHOM_EINVAL;
-  if (precision != GHOM_FP64 && precision != GHOM_FP32_SPLIT) return GHOM_EINVAL;
+  if (!probs || nprob < 1 || nprob > 65535) return create_fail(GHOM_EINVAL, "need 1..65535 problems");
+  if (precision != GHOM_FP64 && precision != GHOM_FP32_SPLIT) return create_fail(GHOM_EINVAL, "unknown precision");
   for (int i = 0; i < nprob; ++i) {
     const ghom_problem& p = probs[i];
-    if (!supported_length(p.nx) || !supported_length(p.ny) || !supported_length(p.nz)) return GHOM_EINVAL;
-    if (!p.phase || p.nphase < 1 || p.nphase > 65536 || p.nsteps < 1 || !p.target) return GHOM_EINVAL;
+    const std::string at = " (problem " + std::to_string(i) + ")";
+    if (!supported_length(p.nx) || !supported_length(p.ny) || !supported_length(p.nz))
+      return create_fail(GHOM_EINVAL, std::string("grid lengths must be among ") + kLengths + at);
+    if (!p.phase || p.nphase < 1 || p.nphase > 65536 || p.nsteps < 1 || !p.target)
+      return create_fail(GHOM_EINVAL, "bad phase map, phase count or history" + at);
     if (p.kind == GHOM_MATERIAL_NEOHOOKEAN) {
-      if (!p.mu || !p.lambda) return GHOM_EINVAL;
+      if (!p.mu || !p.lambda) return create_fail(GHOM_EINVAL, "missing neo-Hookean moduli" + at);
     } else if (p.kind == GHOM_MATERIAL_SVK) {
-      if (!p.C) return GHOM_EINVAL;
+      if (!p.C) return create_fail(GHOM_EINVAL, "missing stiffness tensors" + at);
     } else {
-      return GHOM_EINVAL;
+      return create_fail(GHOM_EINVAL, "unknown material kind" + at);
     }
     for (int c = 0; c < 9; ++c)
-      if (p.mask[c] > 1) return GHOM_EINVAL;
+      if (p.mask[c] > 1) return create_fail(GHOM_EINVAL, "mask entries must be 0 or 1" + at);
   }
   Engine* e = new_engine(precision, device, hip_stream);
-  if (!e) return GHOM_ENOMEM;
+  if (!e) return create_fail(GHOM_ENOMEM, "host allocation failed");
   const int rc = guarded(e, [&]() -> int {
     open_stream(*e, hip_stream);
     std::vector<ProbSpec> specs(nprob);
@@ -1954,6 +1974,7 @@ int ghom_batch_create(ghom_batch** out, const ghom_problem* probs, int nprob, in
   });
   ghom_batch* b = rc == GHOM_OK ? new (std::nothrow) ghom_batch() : nullptr;
   if (!b) {
+    g_create_err = rc != GHOM_OK ? e->err : std::string("host allocation failed");
     destroy_engine(e);
     return rc != GHOM_OK ? rc : GHOM_ENOMEM;
   }
@@ -1968,7 +1989,10 @@ void ghom_batch_destroy(ghom_batch* b) {
   delete b;
 }
 
-const char* ghom_batch_last_error(const ghom_batch* b) { return b && b->e ? b->e->err.c_str() : "null batch"; }
+const char* ghom_batch_last_error(const ghom_batch* b) {
+  if (!b) return g_create_err.empty() ? "null batch" : g_create_err.c_str();
+  return b->e ? b->e->err.c_str() : "null batch";
+}
 
 int ghom_batch_set_tolerances(ghom_batch* b, double newton_tol, double cg_tol, double cg_forcing, int max_newton,
                               int max_cg) {

@@ -1367,14 +1367,13 @@ sum_columns_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, i
   sum_columns_body(d.partials, nparts, K, nmax, layout ? 1 : K, layout ? nparts : 1, d.red + off);
 }
 
-// F += dF with dF the float64 correction: x itself in FP64 mode, the re-projected dF64 in
-// FP32-split mode
+// F += x in FP64 mode (in FP32-split mode the re-projection's inverse pass applies the
+// update itself, zinv_batch<..., ZI_NEWTON>)
 __global__ void __launch_bounds__(kVoxThreads)
 newton_update_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
-  const double* dF = d.dF64 ? d.dF64 : reinterpret_cast<const double*>(d.x);
-  newton_update_body<double>(d.g, d.F, dF, d.partials, blockIdx.x, gridDim.x);
+  newton_update_body<double>(d.g, d.F, reinterpret_cast<const double*>(d.x), d.partials, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kVoxThreads)

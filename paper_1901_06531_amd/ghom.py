@@ -165,7 +165,7 @@ class Solver:
         rc = lib().ghom_create(ctypes.byref(self._c), *self.shape, *[float(v) for v in lengths],
                                int(precision), int(device), stream)
         if rc != 0:
-            raise GhomError(rc, "ghom_create failed for shape %s" % (self.shape,))
+            raise GhomError(rc, "ghom_create failed for shape %s: %s" % (self.shape, lib().ghom_last_error(None).decode()))
 
     # -- plumbing ------------------------------------------------------------------------
     def _check(self, rc):
@@ -402,7 +402,7 @@ class Batch:
                                      int(device), stream)
         self._keep = None
         if rc != 0:
-            raise GhomError(rc, "ghom_batch_create failed")
+            raise GhomError(rc, "ghom_batch_create failed: %s" % lib().ghom_batch_last_error(None).decode())
 
     def _check(self, rc):
         if rc != 0:

@@ -41,6 +41,7 @@ def test_argument_checks_need_no_gpu():
     out = ctypes.c_void_p()
     # unsupported grid length and bad precision are rejected before any device call
     assert L.ghom_create(ctypes.byref(out), 10, 16, 16, 1.0, 1.0, 1.0, 0, 0, None) == -1
+    assert b"grid lengths must be among" in L.ghom_last_error(None)
     assert L.ghom_create(ctypes.byref(out), 16, 16, 16, 1.0, 1.0, 1.0, 7, 0, None) == -1
     assert L.ghom_create(ctypes.byref(out), 16, 16, 16, -1.0, 1.0, 1.0, 0, 0, None) == -1
     assert L.ghom_create(None, 16, 16, 16, 1.0, 1.0, 1.0, 0, 0, None) == -1
