@@ -136,7 +136,17 @@ constexpr int pow2_floor(int v) {
 }
 
 // LDS budget per workgroup, in complex values
-template <typename T> constexpr int lds_cx() { return sizeof(T) == 8 ? 4096 : 8192; }
+// LDS budget of a column-pass workgroup (KiB) per precision: 32 KiB in float32 leaves room
+// for several workgroups per CU on short lines (n = 96, 192) without changing n = 256
+#ifndef GHOM_CLDS_KB_F32
+#define GHOM_CLDS_KB_F32 32
+#endif
+#ifndef GHOM_CLDS_KB_F64
+#define GHOM_CLDS_KB_F64 64
+#endif
+template <typename T> constexpr int lds_cx() {
+  return (sizeof(T) == 8 ? GHOM_CLDS_KB_F64 : GHOM_CLDS_KB_F32) * 1024 / (2 * (int)sizeof(T));
+}
 
 // column passes: A threads per line, TC lines per workgroup (at most TCMAX)
 template <typename T, int A, int B, int TCMAX = 64, int MAXT = 256> struct ColCfg {
@@ -155,7 +165,16 @@ template <typename T, int A, int B, int TCMAX = 64, int MAXT = 256> struct ColCf
 #ifndef GHOM_ZLP
 #define GHOM_ZLP 1
 #endif
-template <typename T> constexpr int zlds_cx() { return sizeof(T) == 8 ? 5120 : 10240; }
+// LDS budget of a z-pass workgroup (KiB) per precision (bounds the lines per workgroup)
+#ifndef GHOM_ZLDS_KB_F32
+#define GHOM_ZLDS_KB_F32 24
+#endif
+#ifndef GHOM_ZLDS_KB_F64
+#define GHOM_ZLDS_KB_F64 80
+#endif
+template <typename T> constexpr int zlds_cx() {
+  return (sizeof(T) == 8 ? GHOM_ZLDS_KB_F64 : GHOM_ZLDS_KB_F32) * 1024 / (2 * (int)sizeof(T));
+}
 template <typename T, int A, int B> struct ZCfg {
   static constexpr int N = A * B;
   static constexpr int R = N + B;  // LDS complex values per line: exchange rows padded to A + 1
