@@ -135,7 +135,6 @@ constexpr int pow2_floor(int v) {
   return p;
 }
 
-// LDS budget per workgroup, in complex values
 // LDS budget of a column-pass workgroup (KiB) per precision: 32 KiB in float32 leaves room
 // for several workgroups per CU on short lines (n = 96, 192) without changing n = 256
 #ifndef GHOM_CLDS_KB_F32
@@ -725,6 +724,117 @@ struct ZfwdArgs {
   int pstride;                // Z_CONST sums: column k of block bx at partials[k * pstride + bx]
 };
 
+// Staged per-voxel loops in the z passes: every load of a thread's voxels is issued before
+// the first of them is used (in a plain loop the stores of one voxel hold back the loads of
+// the next, since the compiler cannot rule out that they alias).  It costs registers, so it
+// is taken where it was measured faster at 256^3: the float32 CG passes (forward 0.651 ->
+// 0.578 ms, inverse 0.676 -> 0.664 ms) and the float64 Newton update (0.998 -> 0.755 ms);
+// the float64 CG passes and the residual pass lose occupancy and run slower with it.
+#ifndef GHOM_ZPF_CG32
+#define GHOM_ZPF_CG32 1
+#endif
+#ifndef GHOM_ZPF_CG64
+#define GHOM_ZPF_CG64 0
+#endif
+#ifndef GHOM_ZPF_ZINV
+#define GHOM_ZPF_ZINV 1
+#endif
+#ifndef GHOM_ZPF_NEWTON
+#define GHOM_ZPF_NEWTON 1
+#endif
+template <typename T> constexpr bool zpf_cg() { return sizeof(T) == 4 ? GHOM_ZPF_CG32 != 0 : GHOM_ZPF_CG64 != 0; }
+
+// CG forward pass, per-voxel stage: p update and K : p of this thread's voxels into LDS;
+// returns this thread's share of p : K : p
+template <typename T, int LP, int NT, int NZ, int R, int MODE, typename TIN>
+__device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, TIN>& args, long long line0,
+                                               long long nlines, T beta, T* __restrict__ ldsr) {
+  constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
+  constexpr int KS = MODE == Z_NH ? kNHState : (MODE == Z_SVK ? 9 : 15);
+  const long long N = g.N;
+  long long vx[IT];
+  bool ok[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = threadIdx.x + it * NT;
+    const int lp = t / NZ, z = t - lp * NZ;
+    ok[it] = t < 2 * LP * NZ && line0 + lp < nlines;
+    vx[it] = ok[it] ? (line0 + lp) * NZ + z : 0;  // voxel 0 stands in (in bounds) for idle slots
+  }
+  T dv[IT][9];
+  if (args.update_p == 2) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) dv[it][c] = (T)args.b[c * N + vx[it]];
+  } else if (args.update_p == 1) {
+    T rv[IT][9];
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        rv[it][c] = args.r[c * N + vx[it]];
+        dv[it][c] = args.p[c * N + vx[it]];
+      }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) dv[it][c] = rv[it][c] + beta * dv[it][c];
+  } else {
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) dv[it][c] = args.p[c * N + vx[it]];
+  }
+  T st[IT][KS];
+  T sv[IT];
+  int ph[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) st[it][k] = args.state[k * N + vx[it]];
+    if constexpr (MODE != Z_NH) {
+      ph[it] = args.phase[vx[it]];
+      sv[it] = args.has_scale ? args.state[KS * N + vx[it]] : (T)1;
+    }
+  }
+  double pkp = 0.0;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = threadIdx.x + it * NT;
+    if (t >= 2 * LP * NZ) break;
+    const int lp = t / NZ, z = t - lp * NZ;
+    T val[9];
+    if (ok[it]) {
+      const T* d = dv[it];
+      if (args.update_p == 2) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          args.r[c * N + vx[it]] = d[c];
+          args.p[c * N + vx[it]] = d[c];
+        }
+      } else if (args.update_p == 1) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) args.p[c * N + vx[it]] = d[c];
+      }
+      if constexpr (MODE == Z_NH) tangent_nh(st[it], d, val);
+      else if constexpr (MODE == Z_SVK) tangent_svk(st[it], sv[it], args.C6 + 36 * ph[it], d, val);
+      else tangent_visco(st[it], st[it] + 9, sv[it], args.C6 + 36 * ph[it], d, val);
+      if (args.partials) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) pkp += (double)d[c] * (double)val[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) val[c] = 0;
+    }
+    const int pair = lp >> 1, part = lp & 1;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * R + z) + part] = val[c];
+  }
+  return pkp;
+}
+
 template <typename T, int A, int B, int MODE, typename TIN>
 __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& args, int bx) {
   using Cfg = ZCfg<T, A, B>;
@@ -745,6 +855,9 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   int bad = 0;
   const T beta = (CG && args.update_p == 1) ? (T)args.sc->beta : (T)0;
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
+  if constexpr (CG && zpf_cg<T>()) {
+    pkp = zfwd_cg_fill<T, LP, NT, NZ, R, MODE>(g, args, line0, nlines, beta, ldsr);
+  } else
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
     const long long line = line0 + lp;
@@ -948,6 +1061,73 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
   for (int c = 0; c < (ZM == ZI_NEWTON ? 9 : 1); ++c) fs[c] = 0.0;
   const TOUT alpha = ZM == ZI_CG ? (TOUT)args.sc->alpha : (TOUT)0;
+  if constexpr ((ZM == ZI_CG && zpf_cg<TOUT>() && GHOM_ZPF_ZINV) || (ZM == ZI_NEWTON && GHOM_ZPF_NEWTON)) {
+    // every load of this thread's voxels first, then the updates and stores
+    constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
+    const long long N = g.N;
+    long long vx[IT];
+    bool ok[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int t = threadIdx.x + it * NT;
+      const int lp = t / NZ, z = t - lp * NZ;
+      ok[it] = t < 2 * LP * NZ && line0 + lp < nlines;
+      vx[it] = ok[it] ? (line0 + lp) * NZ + z : 0;  // voxel 0 stands in (in bounds) for idle slots
+    }
+    if constexpr (ZM == ZI_CG) {
+      TOUT xv[IT][9], pv[IT][9], rv[IT][9];
+      const bool first = args.first;
+#pragma unroll
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const long long i = c * N + vx[it];
+          xv[it][c] = first ? (TOUT)0 : args.x[i];
+          pv[it][c] = args.p[i];
+          rv[it][c] = args.r[i];
+        }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int t = threadIdx.x + it * NT;
+        if (!ok[it]) continue;
+        const int lp = t / NZ, z = t - lp * NZ;
+        const int pair = lp >> 1, part = lp & 1;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
+          const long long i = c * N + vx[it];
+          const TOUT xn = xv[it][c] + alpha * pv[it][c];
+          const TOUT rn = rv[it][c] - alpha * o;
+          args.x[i] = xn;
+          args.r[i] = rn;
+          acc += (double)rn * (double)rn;
+        }
+      }
+    } else {
+      double fv[IT][9];
+#pragma unroll
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) fv[it][c] = args.F[c * N + vx[it]];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int t = threadIdx.x + it * NT;
+        if (!ok[it]) continue;
+        const int lp = t / NZ, z = t - lp * NZ;
+        const int pair = lp >> 1, part = lp & 1;
+        double n2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const double o = (double)ldsr[2 * ((c * LP + pair) * R + z) + part];
+          const double fn = fv[it][c] + o;
+          args.F[c * N + vx[it]] = fn;
+          n2 += o * o;
+          fs[c] += fn;
+        }
+        acc = fmax(acc, n2);
+      }
+    }
+  } else
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
     const long long line = line0 + lp;
