@@ -225,18 +225,19 @@ enum {
                               0: keep none (and drop those kept) */
 };
 
-/* Selects a kernel variant.  For the x-pass keys: 0 = pick the faster variant by timing
- * both on this GPU and grid (done by ghom_create; setting 0 re-times), 1 = "rows" (one
+/* Selects a kernel variant.  For the x-pass keys: 0 = pick the fastest variant by timing
+ * each on this GPU and grid (done by ghom_create; setting 0 re-times), 1 = "rows" (one
  * thread transforms the three components of a tensor row in turn), 2 = "groups" (three
- * thread groups, one per component, meeting in LDS).  Both compute the same operator. */
+ * thread groups, one per component, meeting in LDS), 3 = "rows" compiled for at least two
+ * wavefronts per SIMD (fewer registers per thread).  All compute the same operator. */
 int ghom_set_option(ghom_ctx *ctx, int key, int value);
 
 /* GHOM_OPT_ZSLABS: the y-forward, x (projection) and y-inverse passes are run slab by slab
  * over ranges of kz planes, so that a slab's intermediate spectrum can stay in the GPU's
  * last-level cache between the three passes (1 = one launch per pass). */
 
-/* Reads the current value of an option (for the x-pass keys: the variant in use, 1 or 2,
- * once tuned). */
+/* Reads the current value of an option (for the x-pass keys: the variant in use, 1, 2 or
+ * 3, once tuned). */
 int ghom_get_option(ghom_ctx *ctx, int key, int *value);
 
 /* ---- measurement ------------------------------------------------------------------ */

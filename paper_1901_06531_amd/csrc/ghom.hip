@@ -52,7 +52,7 @@ struct ProfRec {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
 
-enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2 };
+enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2, XPROJ_ROWS_CAPPED = 3 };
 
 struct ShapeClass {
   int nx = 0, ny = 0, nz = 0, kind = 0;
@@ -269,11 +269,14 @@ void launch_xproj_variant(Engine& e, ShapeClass& c, int variant, int role, Slab 
   with_split(c.nx, [&](auto s) {
     using S = decltype(s);
     const long long ncols = (long long)c.ny * sl.nkz;
-    if (variant == XPROJ_ROWS) {
+    if (variant == XPROJ_ROWS || variant == XPROJ_ROWS_CAPPED) {
       using Cfg = XRowsCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B>), dim3(grid, 3, (unsigned)c.probs.size()), dim3(Cfg::NT), 0,
-                         e.stream, e.ddesc, c.ids, role, sl);
+      const dim3 gd(grid, 3, (unsigned)c.probs.size());
+      if (variant == XPROJ_ROWS)
+        hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B, 1>), gd, dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl);
+      else
+        hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B, 2>), gd, dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl);
     } else {
       using Cfg = XCfg<T, S::A, S::B>;
       const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
@@ -302,15 +305,15 @@ void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre) {
   }
 }
 
-// Autotuner: times both x-pass variants on the class's (zeroed, unused) spectra with HIP
-// events and keeps the faster one for this precision and shape.
+// Autotuner: times the x-pass variants on the class's (zeroed, unused) spectra with HIP
+// events and keeps the fastest for this precision and shape.
 template <typename T>
 void tune_xproj(Engine& e, ShapeClass& c) {
   hipEvent_t e0 = get_event(e), e1 = get_event(e);
   float best = 0.f;
   int best_v = XPROJ_ROWS;
   const Slab full{0, c.g.nzh};
-  for (int v : {XPROJ_ROWS, XPROJ_GROUPS}) {
+  for (int v : {XPROJ_ROWS, XPROJ_GROUPS, XPROJ_ROWS_CAPPED}) {
     launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full);  // warm-up
     HIPCALL(hipGetLastError());
     float tmin = 0.f;
@@ -1814,7 +1817,7 @@ static void drop_graphs(Engine& e) {
 
 static int set_option(Engine& e, int key, int value) {
   if (key == GHOM_OPT_XPROJ_F64 || key == GHOM_OPT_XPROJ_F32) {
-    if (value < XPROJ_TUNED || value > XPROJ_GROUPS) fail(GHOM_EINVAL, "x-pass variant must be 0, 1 or 2");
+    if (value < XPROJ_TUNED || value > XPROJ_ROWS_CAPPED) fail(GHOM_EINVAL, "x-pass variant must be 0, 1, 2 or 3");
     for (auto& cl : e.C) {
       cl.xproj_var[key == GHOM_OPT_XPROJ_F64 ? 0 : 1] = value;
       if (value == XPROJ_TUNED) tune_class(e, cl, key == GHOM_OPT_XPROJ_F64 ? 0 : 1);

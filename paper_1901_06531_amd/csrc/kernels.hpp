@@ -272,10 +272,14 @@ __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restr
 // ---------------------------------------------------------------------------------
 // x pass with the modified projection (eq. 22), for one tensor row per blockIdx.y
 // ---------------------------------------------------------------------------------
+// No array indexed at run time lives in this struct or in the x-pass bodies: such an array
+// is placed in per-lane scratch memory, which every thread would write at kernel start.
 struct ProjParams {
-  unsigned mask;      // bit c set: component c is stress-controlled (IJ)
-  double post;        // output factor (scale / N: fixes the unnormalized transforms)
-  double off[9];      // value subtracted at xi = 0 on stress-controlled components
+  unsigned mask;        // bit c set: component c is stress-controlled (IJ)
+  double post;          // output factor (scale / N: fixes the unnormalized transforms)
+  const double* pbar;   // nullable: N * pbar[c] is subtracted at xi = 0 (stress-controlled c)
+  double n;             // N
+  __device__ double off(int c) const { return pbar ? n * pbar[c] : 0.0; }
 };
 
 __device__ __forceinline__ int signed_k(int k, int n) { return k <= (n - 1) / 2 ? k : k - n; }
@@ -365,7 +369,7 @@ __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* 
     v[e] = s * (l == 0 ? xx : (l == 1 ? xy : xz));
   }
   if (ok && ky == 0 && kz == 0 && q == 0) {  // xi = 0: eq. (22) keeps stress-controlled components
-    v[0] = ((pp.mask >> comp) & 1u) ? cx<T>{(a0.re - (T)pp.off[comp]) * post, a0.im * post} : cx<T>{0, 0};
+    v[0] = ((pp.mask >> comp) & 1u) ? cx<T>{(a0.re - (T)pp.off(comp)) * post, a0.im * post} : cx<T>{0, 0};
   }
   __syncthreads();
   four_step_second_inv<A, B, +1>(v, q, tw, [&](int c, int a, cx<T> z) { E[c * RS + a * TC + j] = z; });
@@ -417,7 +421,7 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
   const bool hold0 = ok && ky == 0 && kz == 0 && q == 0;
   auto xi_x = [&](int e) { return (T)(signed_k(q + A * e, g.nx) * g.invL[0]); };
   cx<T> s[B];
-  cx<T> a0[3];
+  __shared__ cx<T> a0s[3];  // values at xi = 0, written and read by the thread that holds it
 #pragma unroll
   for (int e = 0; e < B; ++e) s[e] = cx<T>{0, 0};
   auto load_comp = [&](int l, cx<T>* v) {
@@ -446,7 +450,7 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
     four_step_second<A, B, -1>(v, q, [&](int c, int a) { return lds[c * RS + a * TC + j]; });
 #pragma unroll
     for (int e = 0; e < B; ++e) s[e] = s[e] + v[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
-    a0[l] = v[0];
+    if (hold0) a0s[l] = v[0];
   }
 #pragma unroll
   for (int e = 0; e < B; ++e) {
@@ -463,7 +467,8 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
     for (int e = 0; e < B; ++e) v[e] = s[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
     if (hold0) {  // xi = 0: eq. (22) keeps stress-controlled components (minus P-bar)
       const int c = 3 * row + l;
-      v[0] = ((pp.mask >> c) & 1u) ? cx<T>{(a0[l].re - (T)pp.off[c]) * post, a0[l].im * post} : cx<T>{0, 0};
+      const cx<T> a0 = a0s[l];
+      v[0] = ((pp.mask >> c) & 1u) ? cx<T>{(a0.re - (T)pp.off(c)) * post, a0.im * post} : cx<T>{0, 0};
     }
     __syncthreads();
     four_step_second_inv<A, B, +1>(v, q, tw, [&](int c, int a, cx<T> z) { lds[c * RS + a * TC + j] = z; });
@@ -1385,7 +1390,8 @@ __device__ __forceinline__ ProjParams proj_params(const ProbDesc& d, int role) {
   pp.mask = d.mask;
   const double n = (double)d.g.N;
   pp.post = (role == ROLE_RESID ? -1.0 : 1.0) / n;
-  for (int c = 0; c < 9; ++c) pp.off[c] = role == ROLE_RESID ? n * d.pbar[c] : 0.0;
+  pp.pbar = role == ROLE_RESID ? d.pbar : nullptr;
+  pp.n = n;
   return pp;
 }
 
@@ -1438,8 +1444,17 @@ ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int rol
                            blockIdx.x);
 }
 
-template <typename T, int A, int B>
-__global__ void __launch_bounds__((XRowsCfg<T, A, B>::NT))
+// WAVES > 1: at least that many waves per SIMD, a register cap (the "rows, capped" variant;
+// it pays where the uncapped kernel runs one wave per SIMD and spills little when capped).
+// The cap is lowered to what the workgroup's LDS allows (160 KiB per CU, 4 SIMDs).
+template <typename T, int A, int B, int WAVES> constexpr int xrows_waves() {
+  using Cfg = XRowsCfg<T, A, B>;
+  constexpr int lds = Cfg::LDS * (int)sizeof(cx<T>) + 64;
+  constexpr int per_simd = (160 * 1024 / lds) * (Cfg::NT / 64) / 4;
+  return cmax(1, cmin(WAVES, per_simd));
+}
+template <typename T, int A, int B, int WAVES>
+__global__ void __launch_bounds__((XRowsCfg<T, A, B>::NT), (xrows_waves<T, A, B, WAVES>()))
 xproj_rows_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
