@@ -251,7 +251,7 @@ int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name, int
 }
 
 template <typename T, int DIR>
-void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string& name) {
+void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string& name, int alpha_nparts = 0) {
   with_split(c.ny, [&](auto s) {
     using S = decltype(s);
     using Cfg = ColCfg<T, S::A, S::B>;
@@ -259,7 +259,7 @@ void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string
     const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
     timed(e, name, [&] {
       hipLaunchKernelGGL((ypass_batch<T, S::A, S::B, DIR>), dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0,
-                         e.stream, e.ddesc, c.ids, role, sl);
+                         e.stream, e.ddesc, c.ids, role, sl, alpha_nparts);
     });
   });
 }
@@ -288,9 +288,10 @@ void launch_xproj_variant(Engine& e, ShapeClass& c, int variant, int role, Slab 
 
 template <typename T> int& xproj_choice(ShapeClass& c) { return c.xproj_var[sizeof(T) == 8 ? 0 : 1]; }
 
-// y forward, x with the projection, y inverse; kz-slab by slab
+// y forward, x with the projection, y inverse; kz-slab by slab.  alpha_nparts > 0 (a CG
+// step): the first y pass also sets alpha from the forward pass's partials.
 template <typename T>
-void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre) {
+void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre, int alpha_nparts = 0) {
   const std::string t = tname<T>();
   const std::string n2 = pre + "yfwd_" + t, n3 = pre + "xproj_" + t, n4 = pre + "yinv_" + t;
   const int nzh = c.g.nzh;
@@ -299,7 +300,7 @@ void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre) {
   const int v = xproj_choice<T>(c) == XPROJ_TUNED ? XPROJ_ROWS : xproj_choice<T>(c);
   for (int kz0 = 0; kz0 < nzh; kz0 += per) {
     const Slab sl{kz0, std::min(per, nzh - kz0)};
-    launch_ypass<T, -1>(e, c, role, sl, n2);
+    launch_ypass<T, -1>(e, c, role, sl, n2, kz0 == 0 ? alpha_nparts : 0);
     timed(e, n3, [&] { launch_xproj_variant<T>(e, c, v, role, sl); });
     launch_ypass<T, +1>(e, c, role, sl, n4);
   }
@@ -380,13 +381,7 @@ int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
   if (c.kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p, "op_zfwd_" + t);
   else if (c.kind == MAT_SVK) gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
   else gz = launch_zfwd<T, Z_VISCO, T>(e, c, role, update_p, "op_zfwd_" + t);
-  if (role == ROLE_OP_CG) {
-    timed(e, "cg_scalar", [&] {
-      hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
-                         c.ids, gz, 1);
-    });
-  }
-  middle_passes<T>(e, c, role, "op_");
+  middle_passes<T>(e, c, role, "op_", role == ROLE_OP_CG ? gz : 0);
   if (role == ROLE_OP_CG) launch_zinv<T, T, ZI_CG>(e, c, role, "op_zinv_" + t, update_p == 2 ? 1 : 0);
   else launch_zinv<T, T, ZI_PLAIN>(e, c, role, "op_zinv_" + t);
   return gz;
@@ -532,9 +527,9 @@ void cg_solve(Engine& e, double* t_ms) {
       for (auto& c : e.C) {
         if (!all_classes && !class_active(e, c)) continue;
         const int gz = operator_apply<T>(e, c, ROLE_OP_CG, (first && i == 0) ? 2 : 1);
-        timed(e, "cg_scalar", [&] {
-          hipLaunchKernelGGL(cg_scalar_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
-                             c.ids, gz, 2);
+        timed(e, "cg_beta", [&] {
+          hipLaunchKernelGGL(cg_beta_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
+                             c.ids, gz);
         });
       }
     }

@@ -1230,31 +1230,51 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ bas
   return block_sum<NT>((a0 + a1) + (a2 + a3), red);
 }
 
-// which: 1 = alpha (from p.Ap), 2 = beta (from the new r.r)
-__device__ __forceinline__ void cg_scalar_body(CGScalars* sc, const double* __restrict__ partials, int nparts,
-                                               int which) {
+// beta = r'.r' / r.r from the inverse z pass's partials, the iteration count and the stop
+// test (one block)
+__device__ __forceinline__ void cg_beta_body(CGScalars* sc, const double* __restrict__ partials, int nparts) {
   __shared__ double red[kRedThreads / 64];
   if (sc->done) return;
   const double s = reduce_partials(partials, nparts, 1, red);
   if (threadIdx.x != 0) return;
-  if (which == 1) {
+  sc->beta = s / sc->rr;
+  sc->rr = s;
+  sc->it += 1;
+  if (s <= sc->thresh) {
+    sc->done = 1;
+    sc->status = 1;
+  } else if (sc->it >= sc->max_it) {
+    sc->done = 1;
+    sc->status = 3;
+  }
+}
+
+// alpha = rr / p.Ap by one block of NT threads with
+// eight partials in flight per thread.  It is run by the first block of the first y pass of
+// a CG step, which starts after the forward z pass has written every partial; the inverse z
+// pass, the first reader of alpha, starts after the y pass has ended.
+template <int NT>
+__device__ __forceinline__ void cg_alpha_block(CGScalars* sc, const double* __restrict__ partials, int nparts) {
+  static_assert(NT % 64 == 0, "whole wavefronts (block_sum)");
+  __shared__ double red[NT / 64];
+  if (sc->done) return;  // no other block writes sc during this kernel: the same for all threads
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = 0.0;
+  int i = threadIdx.x;
+  for (; i + 7 * NT < nparts; i += 8 * NT) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += partials[i + k * NT];
+  }
+  for (; i < nparts; i += NT) a[0] += partials[i];
+  const double s = block_sum<NT>(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])), red);
+  if (threadIdx.x == 0) {
     sc->pAp = s;
     if (!(s > 0.0) || !isfinite(s)) {
       sc->done = 1;
       sc->status = 2;
     } else {
       sc->alpha = sc->rr / s;
-    }
-  } else {
-    sc->beta = s / sc->rr;
-    sc->rr = s;
-    sc->it += 1;
-    if (s <= sc->thresh) {
-      sc->done = 1;
-      sc->status = 1;
-    } else if (sc->it >= sc->max_it) {
-      sc->done = 1;
-      sc->status = 3;
     }
   }
 }
@@ -1435,11 +1455,17 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
   zfwd_body<T, A, B, MODE, TIN>(d.g, a, blockIdx.x);
 }
 
+// alpha_nparts > 0: block 0 of each problem first sets the CG step's alpha from that many
+// partials of the forward z pass
 template <typename T, int A, int B, int DIR>
 __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
-ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
+ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl, int alpha_nparts) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
+  if (alpha_nparts > 0 && blockIdx.x == 0) {
+    cg_alpha_block<ColCfg<T, A, B>::NT>(d.sc, d.partials, alpha_nparts);
+    __syncthreads();  // a breakdown (done = 1) is seen by every thread of the block below
+  }
   ypass_body<T, A, B, DIR>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
                            blockIdx.x);
 }
@@ -1565,10 +1591,10 @@ __global__ void cg_start_batch(const ProbDesc* __restrict__ D, const int* __rest
 
 // one block per problem
 __global__ void __launch_bounds__(kRedThreads)
-cg_scalar_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int which) {
+cg_beta_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts) {
   const ProbDesc& d = D[ids[blockIdx.x]];
   if (!d.active) return;
-  cg_scalar_body(d.sc, d.partials, nparts, which);
+  cg_beta_body(d.sc, d.partials, nparts);
 }
 
 // layout 0: entry (i, k) at i * K + k; layout 1: at k * nparts + i.  Results go to
