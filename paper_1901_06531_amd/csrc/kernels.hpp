@@ -729,17 +729,18 @@ struct ZfwdArgs {
   int pstride;                // Z_CONST sums: column k of block bx at partials[k * pstride + bx]
 };
 
-// Staged per-voxel loops in the z passes: every load of a thread's voxels is issued before
-// the first of them is used (in a plain loop the stores of one voxel hold back the loads of
-// the next, since the compiler cannot rule out that they alias).  It costs registers, so it
-// is taken where it was measured faster at 256^3: the float32 CG passes (forward 0.651 ->
-// 0.578 ms, inverse 0.676 -> 0.664 ms) and the float64 Newton update (0.998 -> 0.755 ms);
-// the float64 CG passes and the residual pass lose occupancy and run slower with it.
+// Staged per-voxel loops in the z passes: every load of a chunk of a thread's voxels is
+// issued before the first of them is used (in a plain loop the stores of one voxel hold back
+// the loads of the next, since the compiler cannot rule out that they alias).  It costs
+// registers; measured at 256^3: float32 CG passes (all voxels in one chunk) forward 0.651 ->
+// 0.578 ms, inverse 0.676 -> 0.664 ms; float64 CG passes forward (one chunk) 1.270 -> 1.173
+// ms, inverse (chunks of two: one chunk loses occupancy) 1.333 -> 1.308 ms; float64 Newton
+// update 0.998 -> 0.755 ms.  The residual pass (constitutive update fused) runs slower staged.
 #ifndef GHOM_ZPF_CG32
 #define GHOM_ZPF_CG32 1
 #endif
 #ifndef GHOM_ZPF_CG64
-#define GHOM_ZPF_CG64 0
+#define GHOM_ZPF_CG64 1
 #endif
 #ifndef GHOM_ZPF_ZINV
 #define GHOM_ZPF_ZINV 1
@@ -747,95 +748,109 @@ struct ZfwdArgs {
 #ifndef GHOM_ZPF_NEWTON
 #define GHOM_ZPF_NEWTON 1
 #endif
+#ifndef GHOM_ZPF_DEPTH64_FWD
+#define GHOM_ZPF_DEPTH64_FWD 8
+#endif
+#ifndef GHOM_ZPF_DEPTH64_INV
+#define GHOM_ZPF_DEPTH64_INV 2
+#endif
 template <typename T> constexpr bool zpf_cg() { return sizeof(T) == 4 ? GHOM_ZPF_CG32 != 0 : GHOM_ZPF_CG64 != 0; }
+// voxels per chunk of a staged CG loop of trip count it: all of them in float32, at most
+// GHOM_ZPF_DEPTH64_FWD / _INV in float64 (twice the registers per value)
+template <typename T, bool FWD> constexpr int zpf_depth(int it) {
+  return sizeof(T) == 4 ? it : cmin(it, FWD ? GHOM_ZPF_DEPTH64_FWD : GHOM_ZPF_DEPTH64_INV);
+}
 
-// CG forward pass, per-voxel stage: p update and K : p of this thread's voxels into LDS;
-// returns this thread's share of p : K : p
-template <typename T, int LP, int NT, int NZ, int R, int MODE, typename TIN>
+// CG forward pass, per-voxel stage: p update and K : p of this thread's voxels into LDS, in
+// chunks of SD voxels whose loads are all issued first; returns this thread's share of p : K : p
+template <typename T, int LP, int NT, int NZ, int R, int MODE, typename TIN, int SD>
 __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, TIN>& args, long long line0,
                                                long long nlines, T beta, T* __restrict__ ldsr) {
   constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
   constexpr int KS = MODE == Z_NH ? kNHState : (MODE == Z_SVK ? 9 : 15);
   const long long N = g.N;
-  long long vx[IT];
-  bool ok[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int t = threadIdx.x + it * NT;
-    const int lp = t / NZ, z = t - lp * NZ;
-    ok[it] = t < 2 * LP * NZ && line0 + lp < nlines;
-    vx[it] = ok[it] ? (line0 + lp) * NZ + z : 0;  // voxel 0 stands in (in bounds) for idle slots
-  }
-  T dv[IT][9];
-  if (args.update_p == 2) {
-#pragma unroll
-    for (int it = 0; it < IT; ++it)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) dv[it][c] = (T)args.b[c * N + vx[it]];
-  } else if (args.update_p == 1) {
-    T rv[IT][9];
-#pragma unroll
-    for (int it = 0; it < IT; ++it)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        rv[it][c] = args.r[c * N + vx[it]];
-        dv[it][c] = args.p[c * N + vx[it]];
-      }
-#pragma unroll
-    for (int it = 0; it < IT; ++it)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) dv[it][c] = rv[it][c] + beta * dv[it][c];
-  } else {
-#pragma unroll
-    for (int it = 0; it < IT; ++it)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) dv[it][c] = args.p[c * N + vx[it]];
-  }
-  T st[IT][KS];
-  T sv[IT];
-  int ph[IT];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-#pragma unroll
-    for (int k = 0; k < KS; ++k) st[it][k] = args.state[k * N + vx[it]];
-    if constexpr (MODE != Z_NH) {
-      ph[it] = args.phase[vx[it]];
-      sv[it] = args.has_scale ? args.state[KS * N + vx[it]] : (T)1;
-    }
-  }
   double pkp = 0.0;
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int t = threadIdx.x + it * NT;
-    if (t >= 2 * LP * NZ) break;
-    const int lp = t / NZ, z = t - lp * NZ;
-    T val[9];
-    if (ok[it]) {
-      const T* d = dv[it];
-      if (args.update_p == 2) {
+  for (int c0 = 0; c0 < IT; c0 += SD) {
+    long long vx[SD];
+    bool ok[SD];
+#pragma unroll
+    for (int k = 0; k < SD; ++k) {
+      const int t = threadIdx.x + (c0 + k) * NT;
+      const int lp = t / NZ, z = t - lp * NZ;
+      ok[k] = c0 + k < IT && t < 2 * LP * NZ && line0 + lp < nlines;
+      vx[k] = ok[k] ? (line0 + lp) * NZ + z : 0;  // voxel 0 stands in (in bounds) for idle slots
+    }
+    T dv[SD][9];
+    if (args.update_p == 2) {
+#pragma unroll
+      for (int k = 0; k < SD; ++k)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dv[k][c] = (T)args.b[c * N + vx[k]];
+    } else if (args.update_p == 1) {
+      T rv[SD][9];
+#pragma unroll
+      for (int k = 0; k < SD; ++k)
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-          args.r[c * N + vx[it]] = d[c];
-          args.p[c * N + vx[it]] = d[c];
+          rv[k][c] = args.r[c * N + vx[k]];
+          dv[k][c] = args.p[c * N + vx[k]];
         }
-      } else if (args.update_p == 1) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) args.p[c * N + vx[it]] = d[c];
-      }
-      if constexpr (MODE == Z_NH) tangent_nh(st[it], d, val);
-      else if constexpr (MODE == Z_SVK) tangent_svk(st[it], sv[it], args.C6 + 36 * ph[it], d, val);
-      else tangent_visco(st[it], st[it] + 9, sv[it], args.C6 + 36 * ph[it], d, val);
-      if (args.partials) {
+      for (int k = 0; k < SD; ++k)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) pkp += (double)d[c] * (double)val[c];
-      }
+        for (int c = 0; c < 9; ++c) dv[k][c] = rv[k][c] + beta * dv[k][c];
     } else {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) val[c] = 0;
-    }
-    const int pair = lp >> 1, part = lp & 1;
+      for (int k = 0; k < SD; ++k)
 #pragma unroll
-    for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * R + z) + part] = val[c];
+        for (int c = 0; c < 9; ++c) dv[k][c] = args.p[c * N + vx[k]];
+    }
+    T st[SD][KS];
+    T sv[SD];
+    int ph[SD];
+#pragma unroll
+    for (int k = 0; k < SD; ++k) {
+#pragma unroll
+      for (int j = 0; j < KS; ++j) st[k][j] = args.state[j * N + vx[k]];
+      if constexpr (MODE != Z_NH) {
+        ph[k] = args.phase[vx[k]];
+        sv[k] = args.has_scale ? args.state[KS * N + vx[k]] : (T)1;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < SD; ++k) {
+      const int t = threadIdx.x + (c0 + k) * NT;
+      if (c0 + k >= IT || t >= 2 * LP * NZ) break;
+      const int lp = t / NZ, z = t - lp * NZ;
+      T val[9];
+      if (ok[k]) {
+        const T* d = dv[k];
+        if (args.update_p == 2) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            args.r[c * N + vx[k]] = d[c];
+            args.p[c * N + vx[k]] = d[c];
+          }
+        } else if (args.update_p == 1) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) args.p[c * N + vx[k]] = d[c];
+        }
+        if constexpr (MODE == Z_NH) tangent_nh(st[k], d, val);
+        else if constexpr (MODE == Z_SVK) tangent_svk(st[k], sv[k], args.C6 + 36 * ph[k], d, val);
+        else tangent_visco(st[k], st[k] + 9, sv[k], args.C6 + 36 * ph[k], d, val);
+        if (args.partials) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) pkp += (double)d[c] * (double)val[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) val[c] = 0;
+      }
+      const int pair = lp >> 1, part = lp & 1;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * R + z) + part] = val[c];
+    }
   }
   return pkp;
 }
@@ -861,7 +876,8 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   const T beta = (CG && args.update_p == 1) ? (T)args.sc->beta : (T)0;
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
   if constexpr (CG && zpf_cg<T>()) {
-    pkp = zfwd_cg_fill<T, LP, NT, NZ, R, MODE>(g, args, line0, nlines, beta, ldsr);
+    constexpr int SD = zpf_depth<T, true>((2 * LP * NZ + NT - 1) / NT);
+    pkp = zfwd_cg_fill<T, LP, NT, NZ, R, MODE, TIN, SD>(g, args, line0, nlines, beta, ldsr);
   } else
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
@@ -1067,7 +1083,8 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
   for (int c = 0; c < (ZM == ZI_NEWTON ? 9 : 1); ++c) fs[c] = 0.0;
   const TOUT alpha = ZM == ZI_CG ? (TOUT)args.sc->alpha : (TOUT)0;
   if constexpr ((ZM == ZI_CG && zpf_cg<TOUT>() && GHOM_ZPF_ZINV) || (ZM == ZI_NEWTON && GHOM_ZPF_NEWTON)) {
-    // every load of this thread's voxels first, then the updates and stores
+    // every load of a chunk of this thread's voxels first, then the updates and stores (the
+    // CG update in chunks of zpf_depth voxels, the Newton update all at once)
     constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
     const long long N = g.N;
     long long vx[IT];
@@ -1080,32 +1097,40 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
       vx[it] = ok[it] ? (line0 + lp) * NZ + z : 0;  // voxel 0 stands in (in bounds) for idle slots
     }
     if constexpr (ZM == ZI_CG) {
-      TOUT xv[IT][9], pv[IT][9], rv[IT][9];
+      constexpr int SD = zpf_depth<TOUT, false>(IT);
       const bool first = args.first;
 #pragma unroll
-      for (int it = 0; it < IT; ++it)
+      for (int c0 = 0; c0 < IT; c0 += SD) {
+        TOUT xv[SD][9], pv[SD][9], rv[SD][9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const long long i = c * N + vx[it];
-          xv[it][c] = first ? (TOUT)0 : args.x[i];
-          pv[it][c] = args.p[i];
-          rv[it][c] = args.r[i];
+        for (int k = 0; k < SD; ++k) {
+          const long long v = c0 + k < IT ? vx[c0 + k] : 0;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            const long long i = c * N + v;
+            xv[k][c] = first ? (TOUT)0 : args.x[i];
+            pv[k][c] = args.p[i];
+            rv[k][c] = args.r[i];
+          }
         }
 #pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        const int t = threadIdx.x + it * NT;
-        if (!ok[it]) continue;
-        const int lp = t / NZ, z = t - lp * NZ;
-        const int pair = lp >> 1, part = lp & 1;
+        for (int k = 0; k < SD; ++k) {
+          const int it = c0 + k;
+          if (it >= IT) break;
+          if (!ok[it]) continue;
+          const int t = threadIdx.x + it * NT;
+          const int lp = t / NZ, z = t - lp * NZ;
+          const int pair = lp >> 1, part = lp & 1;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
-          const long long i = c * N + vx[it];
-          const TOUT xn = xv[it][c] + alpha * pv[it][c];
-          const TOUT rn = rv[it][c] - alpha * o;
-          args.x[i] = xn;
-          args.r[i] = rn;
-          acc += (double)rn * (double)rn;
+          for (int c = 0; c < 9; ++c) {
+            const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
+            const long long i = c * N + vx[it];
+            const TOUT xn = xv[k][c] + alpha * pv[k][c];
+            const TOUT rn = rv[k][c] - alpha * o;
+            args.x[i] = xn;
+            args.r[i] = rn;
+            acc += (double)rn * (double)rn;
+          }
         }
       }
     } else {
