@@ -247,13 +247,14 @@ def test_failure_modes_are_reported():
     shape = (8, 8, 8)
     P_end = np.zeros(9)
     P_end[0] = 0.1
-    with ghom.Solver(shape) as s:
-        s.set_material_neohookean(np.zeros(shape, np.uint16), [-1.0], [0.0])
-        s.set_control(synth.mask_full_stress())
-        s.set_history(synth.history_stress_ramp(P_end, 1))
-        with pytest.raises(ghom.GhomError) as e:
-            s.step()
-        assert e.value.name == "ESINGULAR"
+    for prec in (ghom.FP64, ghom.FP32_SPLIT):  # p.Ap < 0 in the first CG step: breakdown
+        with ghom.Solver(shape, precision=prec) as s:
+            s.set_material_neohookean(np.zeros(shape, np.uint16), [-1.0], [0.0])
+            s.set_control(synth.mask_full_stress())
+            s.set_history(synth.history_stress_ramp(P_end, 1))
+            with pytest.raises(ghom.GhomError) as e:
+                s.step()
+            assert e.value.name == "ESINGULAR"
     with ghom.Solver(shape) as s:
         F_end = np.eye(3)
         F_end[0, 0] = -0.5
