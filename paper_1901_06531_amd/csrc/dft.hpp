@@ -16,6 +16,45 @@ namespace ghom {
 
 template <typename T> struct cx { T re, im; };
 
+// Streamed global memory: on long transform lines (n >= GHOM_NT_MIN) every field and spectrum
+// value is read and written once per pass with no reuse in the last-level cache (a float32 CG
+// iteration touches about 184 B per voxel: 386 MB at 128^3 against 256 MB of cache), so loads
+// and stores carry the nontemporal hint.  Measured on this chip: a plain copy 6.29 -> 6.73
+// TB/s, three reads and two writes per element 5.71 -> 6.04 TB/s, a 256^3 CG iteration -7%;
+// a single 32^3..96^3 problem, whose iteration fits in the cache, runs 6-10% slower with it.
+// A complex value moves as one 2-vector (spectra are aligned to a whole complex value).
+#ifndef GHOM_NT_MIN
+#define GHOM_NT_MIN 128
+#endif
+constexpr bool stream_nt(int n) { return n >= GHOM_NT_MIN; }
+template <typename T> using vec2_t = T __attribute__((ext_vector_type(2)));
+template <bool NT, typename T> __device__ __forceinline__ cx<T> ld_cx(const cx<T>* p) {
+  if constexpr (NT) {
+    const vec2_t<T> v = __builtin_nontemporal_load(reinterpret_cast<const vec2_t<T>*>(p));
+    return cx<T>{v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+template <bool NT, typename T> __device__ __forceinline__ void st_cx(cx<T>* p, cx<T> z) {
+  if constexpr (NT) {
+    vec2_t<T> v;
+    v.x = z.re;
+    v.y = z.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<vec2_t<T>*>(p));
+  } else {
+    *p = z;
+  }
+}
+template <bool NT, typename T> __device__ __forceinline__ T ld_s(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T> __device__ __forceinline__ void st_s(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 template <typename T> __host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
 template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }

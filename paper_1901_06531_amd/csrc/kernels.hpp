@@ -242,6 +242,7 @@ __device__ __forceinline__ void four_step_second_inv(const cx<T>* v, int q, cons
 template <typename T, int A, int B, int DIR>
 __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw,
                                            const CGScalars* __restrict__ sc, int bx) {
+  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -257,7 +258,7 @@ __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restr
   const long long rs = g.nzh;
   cx<T> v[B];
 #pragma unroll
-  for (int e = 0; e < B; ++e) v[e] = ok ? H[base + (long long)(q + A * e) * rs] : cx<T>{0, 0};
+  for (int e = 0; e < B; ++e) v[e] = ok ? ld_cx<kNT>(&H[base + (long long)(q + A * e) * rs]) : cx<T>{0, 0};
   four_step_first<A, B, DIR>(v, q, tw);
 #pragma unroll
   for (int c = 0; c < B; ++c) lds[c * RS + q * TC + j] = v[c];
@@ -265,7 +266,7 @@ __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restr
   four_step_second<A, B, DIR>(v, q, [&](int c, int a) { return lds[c * RS + a * TC + j]; });
   if (ok) {
 #pragma unroll
-    for (int e = 0; e < B; ++e) H[base + (long long)(q + A * e) * rs] = v[e];
+    for (int e = 0; e < B; ++e) st_cx<kNT>(&H[base + (long long)(q + A * e) * rs], v[e]);
   }
 }
 
@@ -317,6 +318,7 @@ template <typename T, int A, int B>
 __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
                                                   const cx<T>* __restrict__ tw, const ProjParams& pp,
                                                   const CGScalars* __restrict__ sc, int bx, int by) {
+  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
   using Cfg = XCfg<T, A, B>;
   constexpr int TC = Cfg::TC, RS = Cfg::RS, REG = Cfg::REG;
   __shared__ cx<T> lds[3 * REG];
@@ -343,7 +345,7 @@ __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* 
   const long long cbase = (long long)comp * g.Nh + gcol;
   cx<T> v[B];
 #pragma unroll
-  for (int e = 0; e < B; ++e) v[e] = ok ? H[cbase + (long long)(q + A * e) * rs] : cx<T>{0, 0};
+  for (int e = 0; e < B; ++e) v[e] = ok ? ld_cx<kNT>(&H[cbase + (long long)(q + A * e) * rs]) : cx<T>{0, 0};
   // forward transform along x of this group's component
   four_step_first<A, B, -1>(v, q, tw);
 #pragma unroll
@@ -379,7 +381,7 @@ __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* 
   dft<B, +1>(v);
   if (ok) {
 #pragma unroll
-    for (int e = 0; e < B; ++e) H[cbase + (long long)(q + A * e) * rs] = v[e];
+    for (int e = 0; e < B; ++e) st_cx<kNT>(&H[cbase + (long long)(q + A * e) * rs], v[e]);
   }
 }
 
@@ -398,6 +400,7 @@ template <typename T, int A, int B, bool XPF = (GHOM_XPF < 0 ? sizeof(T) == 4 : 
 __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
                                                 const cx<T>* __restrict__ tw, const ProjParams& pp,
                                                 const CGScalars* __restrict__ sc, int bx, int by) {
+  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
   using Cfg = XRowsCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -427,7 +430,7 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
   auto load_comp = [&](int l, cx<T>* v) {
     const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + gcol;
 #pragma unroll
-    for (int e = 0; e < B; ++e) v[e] = ok ? src[(long long)(q + A * e) * rs] : cx<T>{0, 0};
+    for (int e = 0; e < B; ++e) v[e] = ok ? ld_cx<kNT>(&src[(long long)(q + A * e) * rs]) : cx<T>{0, 0};
   };
   // XPF: the loads of the next component are in flight during this component's transform
   cx<T> nxt[XPF ? B : 1];
@@ -479,7 +482,7 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
     if (ok) {
       cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + gcol;
 #pragma unroll
-      for (int e = 0; e < B; ++e) dst[(long long)(q + A * e) * rs] = v[e];
+      for (int e = 0; e < B; ++e) st_cx<kNT>(&dst[(long long)(q + A * e) * rs], v[e]);
     }
   }
 }
@@ -766,6 +769,7 @@ template <typename T, bool FWD> constexpr int zpf_depth(int it) {
 template <typename T, int LP, int NT, int NZ, int R, int MODE, typename TIN, int SD>
 __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, TIN>& args, long long line0,
                                                long long nlines, T beta, T* __restrict__ ldsr) {
+  constexpr bool kNT = stream_nt(NZ);  // nontemporal streamed accesses
   constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
   constexpr int KS = MODE == Z_NH ? kNHState : (MODE == Z_SVK ? 9 : 15);
   const long long N = g.N;
@@ -786,15 +790,15 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 #pragma unroll
       for (int k = 0; k < SD; ++k)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) dv[k][c] = (T)args.b[c * N + vx[k]];
+        for (int c = 0; c < 9; ++c) dv[k][c] = (T)ld_s<kNT>(&args.b[c * N + vx[k]]);
     } else if (args.update_p == 1) {
       T rv[SD][9];
 #pragma unroll
       for (int k = 0; k < SD; ++k)
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-          rv[k][c] = args.r[c * N + vx[k]];
-          dv[k][c] = args.p[c * N + vx[k]];
+          rv[k][c] = ld_s<kNT>(&args.r[c * N + vx[k]]);
+          dv[k][c] = ld_s<kNT>(&args.p[c * N + vx[k]]);
         }
 #pragma unroll
       for (int k = 0; k < SD; ++k)
@@ -804,7 +808,7 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 #pragma unroll
       for (int k = 0; k < SD; ++k)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) dv[k][c] = args.p[c * N + vx[k]];
+        for (int c = 0; c < 9; ++c) dv[k][c] = ld_s<kNT>(&args.p[c * N + vx[k]]);
     }
     T st[SD][KS];
     T sv[SD];
@@ -812,10 +816,10 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 #pragma unroll
     for (int k = 0; k < SD; ++k) {
 #pragma unroll
-      for (int j = 0; j < KS; ++j) st[k][j] = args.state[j * N + vx[k]];
+      for (int j = 0; j < KS; ++j) st[k][j] = ld_s<kNT>(&args.state[j * N + vx[k]]);
       if constexpr (MODE != Z_NH) {
-        ph[k] = args.phase[vx[k]];
-        sv[k] = args.has_scale ? args.state[KS * N + vx[k]] : (T)1;
+        ph[k] = ld_s<kNT>(&args.phase[vx[k]]);
+        sv[k] = args.has_scale ? ld_s<kNT>(&args.state[KS * N + vx[k]]) : (T)1;
       }
     }
 #pragma unroll
@@ -829,12 +833,12 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
         if (args.update_p == 2) {
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            args.r[c * N + vx[k]] = d[c];
-            args.p[c * N + vx[k]] = d[c];
+            st_s<kNT>(&args.r[c * N + vx[k]], d[c]);
+            st_s<kNT>(&args.p[c * N + vx[k]], d[c]);
           }
         } else if (args.update_p == 1) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) args.p[c * N + vx[k]] = d[c];
+          for (int c = 0; c < 9; ++c) st_s<kNT>(&args.p[c * N + vx[k]], d[c]);
         }
         if constexpr (MODE == Z_NH) tangent_nh(st[k], d, val);
         else if constexpr (MODE == Z_SVK) tangent_svk(st[k], sv[k], args.C6 + 36 * ph[k], d, val);
@@ -857,6 +861,7 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 
 template <typename T, int A, int B, int MODE, typename TIN>
 __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& args, int bx) {
+  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
@@ -887,18 +892,18 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
       const long long vox = line * NZ + z;
       if constexpr (MODE == Z_PLAIN) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) val[c] = (T)args.in[c * g.N + vox];
+        for (int c = 0; c < 9; ++c) val[c] = (T)ld_s<kNT>(&args.in[c * g.N + vox]);
       } else if constexpr (CONST) {
         double f[9], pv[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) f[c] = args.F[c * g.N + vox];
+        for (int c = 0; c < 9; ++c) f[c] = ld_s<kNT>(&args.F[c * g.N + vox]);
         const double sv = args.scale ? args.scale[vox] : 1.0;
         if (!constitutive_point<TIN, KIND>(f, args.phase[vox], sv, args.scale != nullptr, args.mat, pv, args.state_out,
                                            g.N, vox, args.iv))
           bad = 1;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-          args.P[c * g.N + vox] = pv[c];
+          st_s<kNT>(&args.P[c * g.N + vox], pv[c]);
           val[c] = (T)pv[c];
           cs[c] += f[c];
           cs[9 + c] += pv[c];
@@ -993,8 +998,8 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
     const cx<T> Ak = (Zk + Zm) * (T)0.5;
     const cx<T> Bk = mul_i<-1>(Zk - Zm) * (T)0.5;
     const long long l0 = line0 + 2 * pair;
-    if (l0 < nlines) args.H[c * g.Nh + l0 * nzh + kz] = Ak;
-    if (l0 + 1 < nlines) args.H[c * g.Nh + (l0 + 1) * nzh + kz] = Bk;
+    if (l0 < nlines) st_cx<kNT>(&args.H[c * g.Nh + l0 * nzh + kz], Ak);
+    if (l0 + 1 < nlines) st_cx<kNT>(&args.H[c * g.Nh + (l0 + 1) * nzh + kz], Bk);
   }
   if constexpr (CONST) {
     if (bad) atomicOr(args.flag, 1);
@@ -1032,6 +1037,7 @@ struct ZinvArgs {
 
 template <typename T, int A, int B, typename TOUT, int ZM>
 __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>& args, int bx) {
+  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
@@ -1045,8 +1051,8 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
     const int ff = t / nzh, kz = t - ff * nzh;
     const int c = ff / LP, pair = ff - c * LP;
     const long long l0 = line0 + 2 * pair;
-    const cx<T> a = l0 < nlines ? args.H[c * g.Nh + l0 * nzh + kz] : cx<T>{0, 0};
-    const cx<T> b = l0 + 1 < nlines ? args.H[c * g.Nh + (l0 + 1) * nzh + kz] : cx<T>{0, 0};
+    const cx<T> a = l0 < nlines ? ld_cx<kNT>(&args.H[c * g.Nh + l0 * nzh + kz]) : cx<T>{0, 0};
+    const cx<T> b = l0 + 1 < nlines ? ld_cx<kNT>(&args.H[c * g.Nh + (l0 + 1) * nzh + kz]) : cx<T>{0, 0};
     lds[ff * R + kz] = a + mul_i<+1>(b);
     if (kz > 0) lds[ff * R + NZ - kz] = conj(a) + mul_i<+1>(conj(b));
     if ((NZ % 2 == 0) && kz == 0) lds[ff * R + NZ / 2] = cx<T>{0, 0};
@@ -1108,9 +1114,9 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const long long i = c * N + v;
-            xv[k][c] = first ? (TOUT)0 : args.x[i];
-            pv[k][c] = args.p[i];
-            rv[k][c] = args.r[i];
+            xv[k][c] = first ? (TOUT)0 : ld_s<kNT>(&args.x[i]);
+            pv[k][c] = ld_s<kNT>(&args.p[i]);
+            rv[k][c] = ld_s<kNT>(&args.r[i]);
           }
         }
 #pragma unroll
@@ -1127,8 +1133,8 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
             const long long i = c * N + vx[it];
             const TOUT xn = xv[k][c] + alpha * pv[k][c];
             const TOUT rn = rv[k][c] - alpha * o;
-            args.x[i] = xn;
-            args.r[i] = rn;
+            st_s<kNT>(&args.x[i], xn);
+            st_s<kNT>(&args.r[i], rn);
             acc += (double)rn * (double)rn;
           }
         }
@@ -1138,7 +1144,7 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
       for (int it = 0; it < IT; ++it)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) fv[it][c] = args.F[c * N + vx[it]];
+        for (int c = 0; c < 9; ++c) fv[it][c] = ld_s<kNT>(&args.F[c * N + vx[it]]);
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int t = threadIdx.x + it * NT;
@@ -1150,7 +1156,7 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
         for (int c = 0; c < 9; ++c) {
           const double o = (double)ldsr[2 * ((c * LP + pair) * R + z) + part];
           const double fn = fv[it][c] + o;
-          args.F[c * N + vx[it]] = fn;
+          st_s<kNT>(&args.F[c * N + vx[it]], fn);
           n2 += o * o;
           fs[c] += fn;
         }
@@ -1181,7 +1187,7 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
         n2 += (double)o * (double)o;
         fs[c] += fn;
       } else {
-        args.out[i] = o;
+        st_s<kNT>(&args.out[i], o);
         if (args.dot_with) acc += (double)o * (double)args.dot_with[i];
       }
     }
