@@ -219,10 +219,16 @@ enum {
   GHOM_OPT_ZSLABS = 3,     /* number of kz slabs the y and x passes are run in (>= 1)     */
   GHOM_OPT_GRAPHS = 4,     /* 1: CG iterations are captured once into HIP graphs and
                               replayed (not while profiling is on); 0: launched one by one */
-  GHOM_OPT_CHECKPOINTS = 5 /* 1: with the viscoelastic law, keep every accepted increment's
+  GHOM_OPT_CHECKPOINTS = 5, /* 1: with the viscoelastic law, keep every accepted increment's
                               converged F and starting internal variables on the device
                               ((9 + 12) x N float64 each), as ghom_adjoint_grad_scale needs;
                               0: keep none (and drop those kept) */
+  GHOM_OPT_STREAM_NT = 6   /* 1: the transform passes load and store fields and spectra with
+                              the nontemporal hint (no reuse expected in the last-level cache);
+                              0: ordinary cached accesses.  Set at creation to 1 when one CG
+                              iteration of all problems together touches more than 256 MB.
+                              Passes along transform lines of length >= 128 always stream.
+                              Results are the same either way. */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the fastest variant by timing

@@ -16,17 +16,19 @@ namespace ghom {
 
 template <typename T> struct cx { T re, im; };
 
-// Streamed global memory: on long transform lines (n >= GHOM_NT_MIN) every field and spectrum
-// value is read and written once per pass with no reuse in the last-level cache (a float32 CG
-// iteration touches about 184 B per voxel: 386 MB at 128^3 against 256 MB of cache), so loads
-// and stores carry the nontemporal hint.  Measured on this chip: a plain copy 6.29 -> 6.73
-// TB/s, three reads and two writes per element 5.71 -> 6.04 TB/s, a 256^3 CG iteration -7%;
-// a single 32^3..96^3 problem, whose iteration fits in the cache, runs 6-10% slower with it.
+// Streamed global memory: when a context's CG working set exceeds the last-level cache (256
+// MB; a float32 CG iteration touches about 184 B per voxel, 386 MB at 128^3) every field and
+// spectrum value is read and written once per pass with no reuse, so the passes load and store
+// them with the nontemporal hint.  Measured on this chip: a plain copy 6.29 -> 6.73 TB/s,
+// three reads and two writes per element 5.71 -> 6.04 TB/s, a 256^3 CG iteration -7%, the
+// 384-problem batch +6% throughput; a single 32^3..96^3 problem, whose iteration fits in the
+// cache, runs 6-10% slower with it.  Kernels of transform length >= GHOM_NT_MIN are built
+// with the hint only (their problems never fit); shorter ones both ways, chosen per context.
 // A complex value moves as one 2-vector (spectra are aligned to a whole complex value).
 #ifndef GHOM_NT_MIN
 #define GHOM_NT_MIN 128
 #endif
-constexpr bool stream_nt(int n) { return n >= GHOM_NT_MIN; }
+constexpr bool stream_nt_always(int n) { return n >= GHOM_NT_MIN; }
 template <typename T> using vec2_t = T __attribute__((ext_vector_type(2)));
 template <bool NT, typename T> __device__ __forceinline__ cx<T> ld_cx(const cx<T>* p) {
   if constexpr (NT) {

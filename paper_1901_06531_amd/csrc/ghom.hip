@@ -123,6 +123,7 @@ struct Engine {
   double newton_tol = 1e-6, cg_tol = 1e-8, cg_forcing = 0.0;
   int max_newton = 50, max_cg = 5000;
   int zslabs = 1;
+  bool stream_nt = false;  // nontemporal builds of the short-line pass kernels (set at creation)
   bool graphs = false;  // replay captured HIP graphs of CG iterations (not while profiling)
   bool checkpoints = false;  // keep per-increment states of path-dependent laws (adjoint)
   std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, first-iteration flag, iterations
@@ -218,6 +219,14 @@ bool class_active(Engine& e, const ShapeClass& c) {
 }
 
 // ------------------------------------------------------------------ pass launchers ----
+// Calls f with std::true_type when the pass kernels of transform length N are to use their
+// nontemporal build: always for long lines, else as chosen for the context.
+template <int N, typename F> void with_nt(const Engine& e, F&& f) {
+  if constexpr (stream_nt_always(N)) f(std::true_type{});
+  else if (e.stream_nt) f(std::true_type{});
+  else f(std::false_type{});
+}
+
 template <typename T, int MODE, typename TIN>
 int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::string& name) {
   int grid = 0;
@@ -226,9 +235,12 @@ int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::str
     using Cfg = ZCfg<T, S::A, S::B>;
     const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
-    timed(e, name, [&] {
-      hipLaunchKernelGGL((zfwd_batch<T, S::A, S::B, MODE, TIN>), dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT),
-                         0, e.stream, e.ddesc, c.ids, role, update_p);
+    with_nt<S::A * S::B>(e, [&](auto nt) {
+      timed(e, name, [&] {
+        hipLaunchKernelGGL((zfwd_batch<T, S::A, S::B, MODE, TIN, decltype(nt)::value>),
+                           dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role,
+                           update_p);
+      });
     });
   });
   return grid;
@@ -242,9 +254,12 @@ int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name, int
     using Cfg = ZCfg<T, S::A, S::B>;
     const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
-    timed(e, name, [&] {
-      hipLaunchKernelGGL((zinv_batch<T, S::A, S::B, TOUT, ZM>), dim3(grid, 1, (unsigned)c.probs.size()),
-                         dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, first);
+    with_nt<S::A * S::B>(e, [&](auto nt) {
+      timed(e, name, [&] {
+        hipLaunchKernelGGL((zinv_batch<T, S::A, S::B, TOUT, ZM, decltype(nt)::value>),
+                           dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role,
+                           first);
+      });
     });
   });
   return grid;
@@ -257,9 +272,12 @@ void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string
     using Cfg = ColCfg<T, S::A, S::B>;
     const long long ncols = 9LL * c.nx * sl.nkz;
     const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-    timed(e, name, [&] {
-      hipLaunchKernelGGL((ypass_batch<T, S::A, S::B, DIR>), dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0,
-                         e.stream, e.ddesc, c.ids, role, sl, alpha_nparts);
+    with_nt<S::A * S::B>(e, [&](auto nt) {
+      timed(e, name, [&] {
+        hipLaunchKernelGGL((ypass_batch<T, S::A, S::B, DIR, decltype(nt)::value>),
+                           dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role,
+                           sl, alpha_nparts);
+      });
     });
   });
 }
@@ -269,20 +287,25 @@ void launch_xproj_variant(Engine& e, ShapeClass& c, int variant, int role, Slab 
   with_split(c.nx, [&](auto s) {
     using S = decltype(s);
     const long long ncols = (long long)c.ny * sl.nkz;
-    if (variant == XPROJ_ROWS || variant == XPROJ_ROWS_CAPPED) {
-      using Cfg = XRowsCfg<T, S::A, S::B>;
-      const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      const dim3 gd(grid, 3, (unsigned)c.probs.size());
-      if (variant == XPROJ_ROWS)
-        hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B, 1>), gd, dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl);
-      else
-        hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B, 2>), gd, dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl);
-    } else {
-      using Cfg = XCfg<T, S::A, S::B>;
-      const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-      hipLaunchKernelGGL((xproj_groups_batch<T, S::A, S::B>), dim3(grid, 3, (unsigned)c.probs.size()), dim3(Cfg::NT),
-                         0, e.stream, e.ddesc, c.ids, role, sl);
-    }
+    with_nt<S::A * S::B>(e, [&](auto nt) {
+      constexpr bool NTS = decltype(nt)::value;
+      if (variant == XPROJ_ROWS || variant == XPROJ_ROWS_CAPPED) {
+        using Cfg = XRowsCfg<T, S::A, S::B>;
+        const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+        const dim3 gd(grid, 3, (unsigned)c.probs.size());
+        if (variant == XPROJ_ROWS)
+          hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B, 1, NTS>), gd, dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids,
+                             role, sl);
+        else
+          hipLaunchKernelGGL((xproj_rows_batch<T, S::A, S::B, 2, NTS>), gd, dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids,
+                             role, sl);
+      } else {
+        using Cfg = XCfg<T, S::A, S::B>;
+        const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+        hipLaunchKernelGGL((xproj_groups_batch<T, S::A, S::B, NTS>), dim3(grid, 3, (unsigned)c.probs.size()),
+                           dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl);
+      }
+    });
   });
 }
 
@@ -973,10 +996,13 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   };
   std::vector<size_t> off(n);
   size_t total = 0;
+  double cg_bytes = 0.0;  // bytes one CG iteration of every problem touches
   for (size_t p = 0; p < n; ++p) {
     off[p] = total;
     total += sizes(e.C[e.P[p].cls].g);
+    cg_bytes += (double)e.C[e.P[p].cls].g.N * (45.0 * (double)e.tsz + 2.0);
   }
+  e.stream_nt = cg_bytes > 256.0 * 1024 * 1024;  // beyond the last-level cache
   HIPCALL(hipMalloc((void**)&e.arena, total));
   HIPCALL(hipMalloc((void**)&e.ddesc, n * sizeof(ProbDesc)));
   HIPCALL(hipMalloc((void**)&e.sc, n * sizeof(CGScalars)));
@@ -1839,6 +1865,12 @@ static int set_option(Engine& e, int key, int value) {
     drop_graphs(e);
     return GHOM_OK;
   }
+  if (key == GHOM_OPT_STREAM_NT) {
+    if (value != 0 && value != 1) fail(GHOM_EINVAL, "streaming option must be 0 or 1");
+    e.stream_nt = value != 0;
+    drop_graphs(e);
+    return GHOM_OK;
+  }
   fail(GHOM_EINVAL, "unknown option");
 }
 
@@ -1849,6 +1881,7 @@ static int get_option(Engine& e, int key, int* value) {
   else if (key == GHOM_OPT_ZSLABS) *value = e.zslabs;
   else if (key == GHOM_OPT_GRAPHS) *value = e.graphs ? 1 : 0;
   else if (key == GHOM_OPT_CHECKPOINTS) *value = e.checkpoints ? 1 : 0;
+  else if (key == GHOM_OPT_STREAM_NT) *value = e.stream_nt ? 1 : 0;
   else fail(GHOM_EINVAL, "unknown option");
   return GHOM_OK;
 }

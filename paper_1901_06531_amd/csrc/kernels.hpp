@@ -239,10 +239,10 @@ __device__ __forceinline__ void four_step_second_inv(const cx<T>* v, int q, cons
 // ---------------------------------------------------------------------------------
 // y pass: in-place complex transform along y of every spectrum line (c, x, kz)
 // ---------------------------------------------------------------------------------
-template <typename T, int A, int B, int DIR>
+template <typename T, int A, int B, int DIR, bool NTS>
 __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw,
                                            const CGScalars* __restrict__ sc, int bx) {
-  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
+  constexpr bool kNT = NTS;  // nontemporal streamed accesses
   using Cfg = ColCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -314,11 +314,11 @@ template <typename T, int A, int B> struct XCfg {
   static constexpr int NT = 3 * NG;
 };
 
-template <typename T, int A, int B>
+template <typename T, int A, int B, bool NTS>
 __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
                                                   const cx<T>* __restrict__ tw, const ProjParams& pp,
                                                   const CGScalars* __restrict__ sc, int bx, int by) {
-  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
+  constexpr bool kNT = NTS;  // nontemporal streamed accesses
   using Cfg = XCfg<T, A, B>;
   constexpr int TC = Cfg::TC, RS = Cfg::RS, REG = Cfg::REG;
   __shared__ cx<T> lds[3 * REG];
@@ -396,11 +396,11 @@ __device__ __forceinline__ void xproj_groups_body(const Geo& g, Slab sl, cx<T>* 
 #define GHOM_XROWS_MAXT 256
 #endif
 template <typename T, int A, int B> using XRowsCfg = ColCfg<T, A, B, 64, GHOM_XROWS_MAXT>;
-template <typename T, int A, int B, bool XPF = (GHOM_XPF < 0 ? sizeof(T) == 4 : GHOM_XPF != 0)>
+template <typename T, int A, int B, bool NTS, bool XPF = (GHOM_XPF < 0 ? sizeof(T) == 4 : GHOM_XPF != 0)>
 __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
                                                 const cx<T>* __restrict__ tw, const ProjParams& pp,
                                                 const CGScalars* __restrict__ sc, int bx, int by) {
-  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
+  constexpr bool kNT = NTS;  // nontemporal streamed accesses
   using Cfg = XRowsCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
@@ -766,10 +766,10 @@ template <typename T, bool FWD> constexpr int zpf_depth(int it) {
 
 // CG forward pass, per-voxel stage: p update and K : p of this thread's voxels into LDS, in
 // chunks of SD voxels whose loads are all issued first; returns this thread's share of p : K : p
-template <typename T, int LP, int NT, int NZ, int R, int MODE, typename TIN, int SD>
+template <typename T, int LP, int NT, int NZ, int R, int MODE, typename TIN, int SD, bool NTS>
 __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, TIN>& args, long long line0,
                                                long long nlines, T beta, T* __restrict__ ldsr) {
-  constexpr bool kNT = stream_nt(NZ);  // nontemporal streamed accesses
+  constexpr bool kNT = NTS;  // nontemporal streamed accesses
   constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
   constexpr int KS = MODE == Z_NH ? kNHState : (MODE == Z_SVK ? 9 : 15);
   const long long N = g.N;
@@ -859,9 +859,9 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
   return pkp;
 }
 
-template <typename T, int A, int B, int MODE, typename TIN>
+template <typename T, int A, int B, int MODE, typename TIN, bool NTS>
 __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& args, int bx) {
-  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
+  constexpr bool kNT = NTS;  // nontemporal streamed accesses
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
@@ -882,7 +882,7 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
   if constexpr (CG && zpf_cg<T>()) {
     constexpr int SD = zpf_depth<T, true>((2 * LP * NZ + NT - 1) / NT);
-    pkp = zfwd_cg_fill<T, LP, NT, NZ, R, MODE, TIN, SD>(g, args, line0, nlines, beta, ldsr);
+    pkp = zfwd_cg_fill<T, LP, NT, NZ, R, MODE, TIN, SD, NTS>(g, args, line0, nlines, beta, ldsr);
   } else
   for (int t = threadIdx.x; t < 2 * LP * NZ; t += NT) {
     const int lp = t / NZ, z = t - lp * NZ;
@@ -1035,9 +1035,9 @@ struct ZinvArgs {
   const CGScalars* sc;        // early exit (nullable)
 };
 
-template <typename T, int A, int B, typename TOUT, int ZM>
+template <typename T, int A, int B, typename TOUT, int ZM, bool NTS>
 __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>& args, int bx) {
-  constexpr bool kNT = stream_nt(A * B);  // nontemporal streamed accesses
+  constexpr bool kNT = NTS;  // nontemporal streamed accesses
   using Cfg = ZCfg<T, A, B>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
@@ -1446,7 +1446,8 @@ __device__ __forceinline__ ProjParams proj_params(const ProbDesc& d, int role) {
   return pp;
 }
 
-template <typename T, int A, int B, int MODE, typename TIN>
+// NTS (this and the pass kernels below): nontemporal loads and stores of the streamed data
+template <typename T, int A, int B, int MODE, typename TIN, bool NTS>
 __global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
 zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, int update_p) {
   const ProbDesc& d = D[ids[blockIdx.z]];
@@ -1483,12 +1484,12 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
   }
   a.H = reinterpret_cast<cx<T>*>(d.H);
   a.tw = twd<T>(d, 2);
-  zfwd_body<T, A, B, MODE, TIN>(d.g, a, blockIdx.x);
+  zfwd_body<T, A, B, MODE, TIN, NTS>(d.g, a, blockIdx.x);
 }
 
 // alpha_nparts > 0: block 0 of each problem first sets the CG step's alpha from that many
 // partials of the forward z pass
-template <typename T, int A, int B, int DIR>
+template <typename T, int A, int B, int DIR, bool NTS>
 __global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
 ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl, int alpha_nparts) {
   const ProbDesc& d = D[ids[blockIdx.z]];
@@ -1497,7 +1498,7 @@ ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int rol
     cg_alpha_block<ColCfg<T, A, B>::NT>(d.sc, d.partials, alpha_nparts);
     __syncthreads();  // a breakdown (done = 1) is seen by every thread of the block below
   }
-  ypass_body<T, A, B, DIR>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
+  ypass_body<T, A, B, DIR, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
                            blockIdx.x);
 }
 
@@ -1510,27 +1511,27 @@ template <typename T, int A, int B, int WAVES> constexpr int xrows_waves() {
   constexpr int per_simd = (160 * 1024 / lds) * (Cfg::NT / 64) / 4;
   return cmax(1, cmin(WAVES, per_simd));
 }
-template <typename T, int A, int B, int WAVES>
+template <typename T, int A, int B, int WAVES, bool NTS>
 __global__ void __launch_bounds__((XRowsCfg<T, A, B>::NT), (xrows_waves<T, A, B, WAVES>()))
 xproj_rows_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   const ProjParams pp = proj_params(d, role);
-  xproj_rows_body<T, A, B>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
+  xproj_rows_body<T, A, B, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
                            role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int A, int B>
+template <typename T, int A, int B, bool NTS>
 __global__ void __launch_bounds__((XCfg<T, A, B>::NT))
 xproj_groups_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   const ProjParams pp = proj_params(d, role);
-  xproj_groups_body<T, A, B>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
+  xproj_groups_body<T, A, B, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
                              role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int A, int B, typename TOUT, int ZM>
+template <typename T, int A, int B, typename TOUT, int ZM, bool NTS>
 __global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
 zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, int first) {
   const ProbDesc& d = D[ids[blockIdx.z]];
@@ -1554,7 +1555,7 @@ zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
                 : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
     a.dot_with = (role == ROLE_RESID || role == ROLE_ADJ) ? a.out : nullptr;
   }
-  zinv_body<T, A, B, TOUT, ZM>(d.g, a, blockIdx.x);
+  zinv_body<T, A, B, TOUT, ZM, NTS>(d.g, a, blockIdx.x);
 }
 
 template <typename TS, int KIND>

@@ -24,6 +24,7 @@ OPT_XPROJ_F32 = 2
 OPT_ZSLABS = 3
 OPT_GRAPHS = 4
 OPT_CHECKPOINTS = 5
+OPT_STREAM_NT = 6
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
           -6: "EDOMAIN", -7: "ESTATE"}
