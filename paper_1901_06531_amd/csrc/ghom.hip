@@ -116,7 +116,8 @@ struct Engine {
   double* red = nullptr;      // device, 32 per problem
   int* flags = nullptr;       // device, one per problem
   double* ckpt = nullptr;        // adaptive stepping: F at the start of the sub-increment and of the increment
-  CGScalars* host_sc = nullptr;  // two slots of one entry per problem (slot 0 = latest after a solve)
+  CGScalars* host_sc = nullptr;  // one entry per problem, mapped: written by the CG kernels
+  CGScalars* host_sc_dev = nullptr;  // its device address
   hipEvent_t sc_ev[2] = {nullptr, nullptr};
   double* host_red = nullptr;
   int* host_flags = nullptr;
@@ -536,13 +537,17 @@ void cg_solve(Engine& e, double* t_ms) {
     hipLaunchKernelGGL(cg_start_batch, dim3((np + 63) / 64), dim3(64), 0, e.stream, e.ddesc, c.ids, np);
     HIPCALL(hipGetLastError());
   }
-  // The host reads the device-side stop flags one chunk behind: while it waits for the
-  // status copied after chunk k, chunk k+1 is already queued, so the GPU never idles on the
-  // round trip.  Iterations queued after every problem has stopped find their done flag set
-  // and return at once; they change nothing.
+  // The host reads the stop flags one chunk behind: the CG kernels write every problem's
+  // scalars into mapped host memory, and while the host waits for the event after chunk k,
+  // chunk k+1 is already queued, so the GPU never idles on the round trip.  Iterations queued
+  // after every problem has stopped find their done flag set and return at once; they change
+  // nothing.
   int enqueued = 0;
   int chunk = vox >= (1LL << 21) ? 1 : (vox >= (1LL << 18) ? 2 : 8);
   const size_t n = e.P.size();
+  int it_cap = 0;  // no problem runs more CG steps than its max_cg
+  for (size_t p = 0; p < n; ++p)
+    if (e.hdesc[p].active) it_cap = std::max(it_cap, e.hdesc[p].max_cg);
   // k CG iterations of every class (the first one starts the solve when `first`); in graph
   // mode every class is included, since a problem's activity is read by the kernels
   auto launch_iters = [&](int k, bool first, bool all_classes) {
@@ -579,30 +584,27 @@ void cg_solve(Engine& e, double* t_ms) {
     }
     enqueued += k;
   };
-  auto post_status = [&](int slot) {
-    HIPCALL(hipMemcpyAsync(e.host_sc + slot * n, e.sc, n * sizeof(CGScalars), hipMemcpyDeviceToHost, e.stream));
-    HIPCALL(hipEventRecord(e.sc_ev[slot], e.stream));
-  };
+  auto mark = [&](int slot) { HIPCALL(hipEventRecord(e.sc_ev[slot], e.stream)); };
   auto all_done = [&](int slot) {
     HIPCALL(hipEventSynchronize(e.sc_ev[slot]));
+    const volatile CGScalars* hs = e.host_sc;
     for (size_t p = 0; p < n; ++p)
-      if (e.hdesc[p].active && !e.host_sc[slot * n + p].done) return false;
+      if (e.hdesc[p].active && !hs[p].done) return false;
     return true;
   };
   enqueue_chunk(chunk);
-  post_status(0);
+  mark(0);
   int slot = 0;
   for (;;) {
+    if (enqueued > it_cap + 64) fail(GHOM_EHIP, "CG stop flags not seen by the host");
     if (chunk < 8 && vox < (1LL << 21)) chunk *= 2;
     enqueue_chunk(chunk);
-    post_status(1 - slot);
+    mark(1 - slot);
     if (all_done(slot)) break;
     slot = 1 - slot;
   }
-  // the copy behind the last queued chunk holds the same (final) values; wait for it so
-  // that no copy into the slots is in flight when the caller reads slot 0
+  // the chunk queued last returns at once; wait for it, so that the scalars are final
   HIPCALL(hipEventSynchronize(e.sc_ev[1 - slot]));
-  if (slot != 0) std::copy(e.host_sc + n, e.host_sc + 2 * n, e.host_sc);
   // the first iteration writes x; a problem that stopped before it gets x = 0
   bool zeroed = false;
   for (auto& c : e.C)
@@ -1009,7 +1011,10 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   HIPCALL(hipMalloc((void**)&e.red, n * 32 * sizeof(double)));
   HIPCALL(hipMalloc((void**)&e.flags, n * sizeof(int)));
   HIPCALL(hipHostMalloc((void**)&e.hdesc, n * sizeof(ProbDesc), hipHostMallocDefault));
-  HIPCALL(hipHostMalloc((void**)&e.host_sc, 2 * n * sizeof(CGScalars), hipHostMallocDefault));
+  // coherent mapped memory: the CG kernels' stores reach the host without a copy
+  HIPCALL(hipHostMalloc((void**)&e.host_sc, n * sizeof(CGScalars), hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCALL(hipHostGetDevicePointer((void**)&e.host_sc_dev, e.host_sc, 0));
+  std::fill(e.host_sc, e.host_sc + n, CGScalars{});
   for (auto& ev : e.sc_ev) HIPCALL(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   HIPCALL(hipHostMalloc((void**)&e.host_red, n * 32 * sizeof(double), hipHostMallocDefault));
   HIPCALL(hipHostMalloc((void**)&e.host_flags, n * sizeof(int), hipHostMallocDefault));
@@ -1062,6 +1067,7 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
       d.tw32[a] = c.tw32[a];
     }
     d.sc = e.sc + p;
+    d.sc_host = e.host_sc_dev + p;
     d.red = e.red + 32 * p;
     d.flag = e.flags + p;
   }

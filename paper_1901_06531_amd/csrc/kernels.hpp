@@ -1262,22 +1262,27 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ bas
 }
 
 // beta = r'.r' / r.r from the inverse z pass's partials, the iteration count and the stop
-// test (one block)
-__device__ __forceinline__ void cg_beta_body(CGScalars* sc, const double* __restrict__ partials, int nparts) {
+// test (one block); then the scalars are copied to sc_host, which the host reads (also when
+// the step was skipped: a breakdown set in the step's y pass reaches the host this way)
+__device__ __forceinline__ void cg_beta_body(CGScalars* sc, CGScalars* sc_host, const double* __restrict__ partials,
+                                             int nparts) {
   __shared__ double red[kRedThreads / 64];
-  if (sc->done) return;
-  const double s = reduce_partials(partials, nparts, 1, red);
-  if (threadIdx.x != 0) return;
-  sc->beta = s / sc->rr;
-  sc->rr = s;
-  sc->it += 1;
-  if (s <= sc->thresh) {
-    sc->done = 1;
-    sc->status = 1;
-  } else if (sc->it >= sc->max_it) {
-    sc->done = 1;
-    sc->status = 3;
+  if (!sc->done) {  // the same for every thread: only thread 0 below writes sc
+    const double s = reduce_partials(partials, nparts, 1, red);
+    if (threadIdx.x == 0) {
+      sc->beta = s / sc->rr;
+      sc->rr = s;
+      sc->it += 1;
+      if (s <= sc->thresh) {
+        sc->done = 1;
+        sc->status = 1;
+      } else if (sc->it >= sc->max_it) {
+        sc->done = 1;
+        sc->status = 3;
+      }
+    }
   }
+  if (threadIdx.x == 0) *sc_host = *sc;
 }
 
 // alpha = rr / p.Ap by one block of NT threads with
@@ -1426,6 +1431,7 @@ struct ProbDesc {
   const cx<float>* tw32[3];
   double* partials;  // this problem's partial sums
   CGScalars* sc;
+  CGScalars* sc_host;  // the same scalars in mapped host memory (written after each CG step)
   double* red;       // reduced values (32)
   int* flag;         // det F <= 0 flag
   const void* in;    // ROLE_OP_PLAIN / ROLE_PROJ input
@@ -1619,6 +1625,7 @@ __global__ void cg_start_batch(const ProbDesc* __restrict__ D, const int* __rest
   const int stop = !d.active || !(d.rr0 > d.cg_thresh);
   sc->done = stop;
   sc->status = stop ? 1 : 0;
+  *d.sc_host = *sc;
 }
 
 // one block per problem
@@ -1626,7 +1633,7 @@ __global__ void __launch_bounds__(kRedThreads)
 cg_beta_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts) {
   const ProbDesc& d = D[ids[blockIdx.x]];
   if (!d.active) return;
-  cg_beta_body(d.sc, d.partials, nparts);
+  cg_beta_body(d.sc, d.sc_host, d.partials, nparts);
 }
 
 // layout 0: entry (i, k) at i * K + k; layout 1: at k * nparts + i.  Results go to

@@ -1,7 +1,7 @@
 """The transform passes built with nontemporal (streaming) loads and stores give the same bits
-as their cached builds: the hint only changes where the data is kept.  A 32^3 problem, whose
-context picks the cached builds, is run both ways in both precisions; a context whose CG
-iteration touches more than 256 MB picks streaming at creation."""
+as their cached builds: the hint only changes where the data is kept.  Small problems (each
+material law), whose contexts pick the cached builds, are run both ways in both precisions; a
+context whose CG iteration touches more than 256 MB picks streaming at creation."""
 
 import numpy as np
 import pytest
@@ -17,7 +17,7 @@ def _run(w, prec, nt):
     with ghom.Solver(w["shape"], precision=prec) as s:
         s.setup(w)
         s.set_tolerances(1e-10, 1e-11, 1e-5 if prec == ghom.FP32_SPLIT else 0.0)
-        assert s.get_option(ghom.OPT_STREAM_NT) == 0  # 32^3 fits in the last-level cache
+        assert s.get_option(ghom.OPT_STREAM_NT) == 0  # fits in the last-level cache
         s.set_option(ghom.OPT_STREAM_NT, nt)
         assert s.get_option(ghom.OPT_STREAM_NT) == nt
         recs = []
@@ -27,10 +27,22 @@ def _run(w, prec, nt):
         return recs, s.field(ghom.FIELD_F)
 
 
-@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
-def test_streaming_builds_give_the_same_bits(prec):
-    w = synth.workload_particles(n=32, count=8)
+def _workload(law):
+    if law == "nh":
+        w = synth.workload_particles(n=32, count=8)
+    elif law == "svk":
+        w = synth.workload_polycrystal(n=32, ngrains=16)
+    else:
+        from test_gpu_visco import _workload as visco_workload
+        w = visco_workload((16, 16, 16), "mixed")
     w["target"] = w["target"][:2]
+    return w
+
+
+@pytest.mark.parametrize("law", ["nh", "svk", "visco"])
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_streaming_builds_give_the_same_bits(prec, law):
+    w = _workload(law)
     ref, Fr = _run(w, prec, 0)
     got, Fg = _run(w, prec, 1)
     for a, b in zip(ref, got):
