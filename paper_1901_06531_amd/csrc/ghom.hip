@@ -113,14 +113,13 @@ struct Engine {
   char* arena = nullptr;
   size_t np = 0;              // partials per problem
   CGScalars* sc = nullptr;    // device, one per problem
-  double* red = nullptr;      // device, 32 per problem
+  double* red = nullptr;      // device address of host_red (mapped), 32 per problem
   int* flags = nullptr;       // device, one per problem
   double* ckpt = nullptr;        // adaptive stepping: F at the start of the sub-increment and of the increment
   CGScalars* host_sc = nullptr;  // one entry per problem, mapped: written by the CG kernels
   CGScalars* host_sc_dev = nullptr;  // its device address
   hipEvent_t sc_ev[2] = {nullptr, nullptr};
   double* host_red = nullptr;
-  int* host_flags = nullptr;
   double newton_tol = 1e-6, cg_tol = 1e-8, cg_forcing = 0.0;
   int max_newton = 50, max_cg = 5000;
   int zslabs = 1;
@@ -443,13 +442,11 @@ void constitutive(Engine& e) {
     });
     timed(e, "reduce", [&] {
       hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 18, 0, 0,
-                         0);
+                         0, 1);
     });
   }
   const size_t n = e.P.size();
-  HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
-  HIPCALL(hipMemcpyAsync(e.host_flags, e.flags, n * sizeof(int), hipMemcpyDeviceToHost, e.stream));
-  sync(e);
+  sync(e);  // the reduced values are written to mapped host memory
   for (size_t p = 0; p < n; ++p) {
     if (!e.hdesc[p].active) continue;
     Prob& q = e.P[p];
@@ -459,7 +456,7 @@ void constitutive(Engine& e) {
       q.Pavg[i] = e.host_red[32 * p + 9 + i] / N;
     }
     q.state_valid = true;
-    if (e.host_flags[p]) {
+    if (e.host_red[32 * p + kRedFlag] != 0.0) {
       q.state_valid = false;
       q.status = GHOM_EDOMAIN;
       q.msg = "det F <= 0 at some voxel";
@@ -490,19 +487,18 @@ void constitutive_residual(Engine& e) {
       else gz = launch_zfwd<double, Z_CONST_VISCO, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
     }
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gz, 18, 0, 1, 0);
+      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gz, 18, 0, 1, 0,
+                         1);
     });
     middle_passes<double>(e, c, ROLE_RESID, "res_");
     const int gi = launch_zinv<double, double, ZI_PLAIN>(e, c, ROLE_RESID, "res_zinv_f64");
     timed(e, "reduce", [&] {
       hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 1, 0, 0,
-                         kRedB);
+                         kRedB, 0);
     });
   }
   const size_t n = e.P.size();
-  HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
-  HIPCALL(hipMemcpyAsync(e.host_flags, e.flags, n * sizeof(int), hipMemcpyDeviceToHost, e.stream));
-  sync(e);
+  sync(e);  // the reduced values are written to mapped host memory
   for (size_t p = 0; p < n; ++p) {
     if (!e.hdesc[p].active) continue;
     Prob& q = e.P[p];
@@ -515,7 +511,7 @@ void constitutive_residual(Engine& e) {
     const double bb = e.host_red[32 * p + kRedB];
     q.rms_b = std::sqrt(bb / N);
     e.hdesc[p].rr0 = bb;
-    if (e.host_flags[p]) {
+    if (e.host_red[32 * p + kRedFlag] != 0.0) {
       q.state_valid = false;
       q.status = GHOM_EDOMAIN;
       q.msg = "det F <= 0 at some voxel";
@@ -629,7 +625,7 @@ void newton_update(Engine& e, std::vector<double>& crit) {
       const int gi = project64(e, c, ROLE_NEWTON, "reproj");
       timed(e, "reduce", [&] {
         hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 10, 1, 1,
-                           0);
+                           0, 0);
       });
       continue;
     }
@@ -638,12 +634,11 @@ void newton_update(Engine& e, std::vector<double>& crit) {
     });
     timed(e, "reduce", [&] {
       hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 10, 1, 0,
-                         0);
+                         0, 0);
     });
   }
   const size_t n = e.P.size();
-  HIPCALL(hipMemcpyAsync(e.host_red, e.red, n * 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
-  sync(e);
+  sync(e);  // the reduced values are written to mapped host memory
   crit.assign(n, 0.0);
   for (size_t p = 0; p < n; ++p) {
     if (!e.hdesc[p].active) continue;
@@ -919,13 +914,12 @@ void destroy_engine(Engine* e) {
       if (c.tw32[a]) (void)hipFree(c.tw32[a]);
     }
   }
-  void* ptrs[] = {e->arena, e->ddesc, e->sc, e->red, e->flags, e->ckpt};
+  void* ptrs[] = {e->arena, e->ddesc, e->sc, e->flags, e->ckpt};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (e->hdesc) (void)hipHostFree(e->hdesc);
   if (e->host_sc) (void)hipHostFree(e->host_sc);
   if (e->host_red) (void)hipHostFree(e->host_red);
-  if (e->host_flags) (void)hipHostFree(e->host_flags);
   for (auto& kv : e->prof_recs)
     for (auto& pr : kv.second.pending) {
       (void)hipEventDestroy(pr.first);
@@ -1008,7 +1002,6 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   HIPCALL(hipMalloc((void**)&e.arena, total));
   HIPCALL(hipMalloc((void**)&e.ddesc, n * sizeof(ProbDesc)));
   HIPCALL(hipMalloc((void**)&e.sc, n * sizeof(CGScalars)));
-  HIPCALL(hipMalloc((void**)&e.red, n * 32 * sizeof(double)));
   HIPCALL(hipMalloc((void**)&e.flags, n * sizeof(int)));
   HIPCALL(hipHostMalloc((void**)&e.hdesc, n * sizeof(ProbDesc), hipHostMallocDefault));
   // coherent mapped memory: the CG kernels' stores reach the host without a copy
@@ -1016,8 +1009,11 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   HIPCALL(hipHostGetDevicePointer((void**)&e.host_sc_dev, e.host_sc, 0));
   std::fill(e.host_sc, e.host_sc + n, CGScalars{});
   for (auto& ev : e.sc_ev) HIPCALL(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  HIPCALL(hipHostMalloc((void**)&e.host_red, n * 32 * sizeof(double), hipHostMallocDefault));
-  HIPCALL(hipHostMalloc((void**)&e.host_flags, n * sizeof(int), hipHostMallocDefault));
+  // reduced values (sums, maxima, the det F flag) are stored by the reduction kernels into
+  // coherent mapped host memory: the host reads them after a stream synchronisation
+  HIPCALL(hipHostMalloc((void**)&e.host_red, n * 32 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCALL(hipHostGetDevicePointer((void**)&e.red, e.host_red, 0));
+  std::fill(e.host_red, e.host_red + 32 * n, 0.0);
   // twiddles W_n^k = exp(-2 pi i k / n) and device id lists per class
   for (auto& c : e.C) {
     const int ns[3] = {c.nx, c.ny, c.nz};
@@ -1672,9 +1668,8 @@ void visco_history_adjoint(Engine& e, const double* a, double* grad_out) {
       e.hdesc[0].active = 1;
       upload_descs(e);
       const int gi = project64(e, cl, ROLE_ADJ, "adj");
-      hipLaunchKernelGGL(sum_columns_batch, dim3(1), dim3(kRedThreads), 0, e.stream, e.ddesc, cl.ids, gi, 1, 0, 0, 20);
+      hipLaunchKernelGGL(sum_columns_batch, dim3(1), dim3(kRedThreads), 0, e.stream, e.ddesc, cl.ids, gi, 1, 0, 0, 20, 0);
       HIPCALL(hipGetLastError());
-      HIPCALL(hipMemcpyAsync(e.host_red, e.red, 32 * sizeof(double), hipMemcpyDeviceToHost, e.stream));
       sync(e);
       const double rr = e.host_red[20];
       const double tol = std::max(e.cg_tol, forcing(e) * std::sqrt(rr / (double)N));

@@ -63,6 +63,7 @@ struct CGScalars {
 };
 
 constexpr int kRedThreads = 1024;
+constexpr int kRedFlag = 31;  // slot of the det F <= 0 flag in a problem's 32 reduced values
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -1640,10 +1641,12 @@ cg_beta_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int n
 // red[off .. off + K).
 __global__ void __launch_bounds__(kRedThreads)
 sum_columns_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int K, int nmax,
-                  int layout, int off) {
+                  int layout, int off, int with_flag) {
   const ProbDesc& d = D[ids[blockIdx.x]];
   if (!d.active) return;
   sum_columns_body(d.partials, nparts, K, nmax, layout ? 1 : K, layout ? nparts : 1, d.red + off);
+  // the det F <= 0 flag of the constitutive update (set by device atomics) rides along
+  if (with_flag && threadIdx.x == 0) d.red[kRedFlag] = (double)*d.flag;
 }
 
 // F += x in FP64 mode (in FP32-split mode the re-projection's inverse pass applies the
