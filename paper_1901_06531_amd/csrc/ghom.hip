@@ -232,7 +232,7 @@ int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::str
   int grid = 0;
   with_split(c.nz, [&](auto s) {
     using S = decltype(s);
-    using Cfg = ZCfg<T, S::A, S::B>;
+    using Cfg = ZCfg<T, S::A, S::B, zfwd_ntmin<MODE>()>;
     const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
     with_nt<S::A * S::B>(e, [&](auto nt) {
@@ -251,7 +251,7 @@ int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name, int
   int grid = 0;
   with_split(c.nz, [&](auto s) {
     using S = decltype(s);
-    using Cfg = ZCfg<T, S::A, S::B>;
+    using Cfg = ZCfg<T, S::A, S::B, zinv_ntmin<ZM>()>;
     const long long nlines = (long long)c.nx * c.ny;
     grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
     with_nt<S::A * S::B>(e, [&](auto nt) {

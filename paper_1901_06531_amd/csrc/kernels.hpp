@@ -175,13 +175,18 @@ template <typename T, int A, int B, int TCMAX = 64, int MAXT = 256> struct ColCf
 template <typename T> constexpr int zlds_cx() {
   return (sizeof(T) == 8 ? GHOM_ZLDS_KB_F64 : GHOM_ZLDS_KB_F32) * 1024 / (2 * (int)sizeof(T));
 }
-template <typename T, int A, int B> struct ZCfg {
+// NTMIN: a larger thread count for the per-voxel stages of the CG-step z passes (zfwd_ntmin /
+// zinv_ntmin), taken when it leaves fewer thread slots idle in the last round
+template <typename T, int A, int B, int NTMIN = 0> struct ZCfg {
   static constexpr int N = A * B;
   static constexpr int R = N + B;  // LDS complex values per line: exchange rows padded to A + 1
   static constexpr int LP =
       cmax(1, cmin(cmax(GHOM_ZLP, 256 / (9 * A)), cmin(1024 / (9 * A), zlds_cx<T>() / (9 * R))));
   static constexpr int NF = 9 * LP * A;           // threads of the transform phase
-  static constexpr int NT = (NF + 63) / 64 * 64;  // whole wavefronts
+  static constexpr int NT0 = (NF + 63) / 64 * 64;  // whole wavefronts
+  // share of thread slots the per-voxel stage uses (2 LP N voxels over whole rounds of nt)
+  static constexpr int slot_use(int nt) { return 1000 * (2 * LP * N) / (((2 * LP * N + nt - 1) / nt) * nt); }
+  static constexpr int NT = (NTMIN > NT0 && slot_use(NTMIN) > slot_use(NT0)) ? NTMIN : NT0;
 };
 
 // ---------------------------------------------------------------------------------
@@ -707,6 +712,19 @@ __device__ __forceinline__ bool constitutive_point(const double* f, int ph, doub
 // and P goes into the transform.
 enum { Z_PLAIN = 0, Z_NH = 1, Z_SVK = 2, Z_CONST_NH = 3, Z_CONST_SVK = 4, Z_VISCO = 5, Z_CONST_VISCO = 6 };
 
+// Threads per workgroup of the z passes: the CG-step passes (zfwd_ntmin here, zinv_ntmin with
+// the inverse pass) take GHOM_ZNT_MIN_CG threads where that fills the last round of the staged
+// per-voxel loop better (at 256^3: 512 voxels, 2 per thread instead of 2.67 with 192 threads;
+// float32 inverse pass 0.598 -> 0.574 ms, float64 CG passes -3%; 48^3 and 128^3 gain too, 96^3
+// and 192^3, which fill 128 threads exactly, would lose 2-3%); the Newton-level passes run
+// 6-10% slower with more threads and keep the transform's own count.
+#ifndef GHOM_ZNT_MIN_CG
+#define GHOM_ZNT_MIN_CG 256
+#endif
+template <int MODE> constexpr int zfwd_ntmin() {
+  return (MODE == Z_NH || MODE == Z_SVK || MODE == Z_VISCO) ? GHOM_ZNT_MIN_CG : 0;
+}
+
 template <typename T, typename TIN>
 struct ZfwdArgs {
   const TIN* in;              // Z_PLAIN: field to transform (9 planes)
@@ -863,7 +881,7 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 template <typename T, int A, int B, int MODE, typename TIN, bool NTS>
 __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& args, int bx) {
   constexpr bool kNT = NTS;  // nontemporal streamed accesses
-  using Cfg = ZCfg<T, A, B>;
+  using Cfg = ZCfg<T, A, B, zfwd_ntmin<MODE>()>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
@@ -1019,6 +1037,7 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
 // first iteration), r -= alpha A p, partial r.r; ZI_NEWTON: Newton update F += field with
 // the partials of max_x |dF(x)|^2 and of the sums of the new F (float64)
 enum { ZI_PLAIN = 0, ZI_CG = 1, ZI_NEWTON = 2 };
+template <int ZM> constexpr int zinv_ntmin() { return ZM == ZI_CG ? GHOM_ZNT_MIN_CG : 0; }
 
 template <typename T, typename TOUT>
 struct ZinvArgs {
@@ -1039,7 +1058,7 @@ struct ZinvArgs {
 template <typename T, int A, int B, typename TOUT, int ZM, bool NTS>
 __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>& args, int bx) {
   constexpr bool kNT = NTS;  // nontemporal streamed accesses
-  using Cfg = ZCfg<T, A, B>;
+  using Cfg = ZCfg<T, A, B, zinv_ntmin<ZM>()>;
   constexpr int LP = Cfg::LP, NT = Cfg::NT, NZ = A * B, R = Cfg::R;
   __shared__ cx<T> lds[9 * LP * R];
   __shared__ double red[(NT + 63) / 64];
@@ -1455,7 +1474,7 @@ __device__ __forceinline__ ProjParams proj_params(const ProbDesc& d, int role) {
 
 // NTS (this and the pass kernels below): nontemporal loads and stores of the streamed data
 template <typename T, int A, int B, int MODE, typename TIN, bool NTS>
-__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
+__global__ void __launch_bounds__((ZCfg<T, A, B, zfwd_ntmin<MODE>()>::NT))
 zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, int update_p) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
@@ -1539,7 +1558,7 @@ xproj_groups_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, 
 }
 
 template <typename T, int A, int B, typename TOUT, int ZM, bool NTS>
-__global__ void __launch_bounds__((ZCfg<T, A, B>::NT))
+__global__ void __launch_bounds__((ZCfg<T, A, B, zinv_ntmin<ZM>()>::NT))
 zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, int first) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
