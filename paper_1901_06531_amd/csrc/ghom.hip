@@ -269,7 +269,7 @@ template <typename T, int DIR>
 void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string& name, int alpha_nparts = 0) {
   with_split(c.ny, [&](auto s) {
     using S = decltype(s);
-    using Cfg = ColCfg<T, S::A, S::B>;
+    using Cfg = YCfg<T, S::A, S::B>;
     const long long ncols = 9LL * c.nx * sl.nkz;
     const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
     with_nt<S::A * S::B>(e, [&](auto nt) {

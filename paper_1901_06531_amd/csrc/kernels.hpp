@@ -159,6 +159,26 @@ template <typename T, int A, int B, int TCMAX = 64, int MAXT = 256> struct ColCf
   static constexpr int LDS = B * RS;
 };
 
+// y passes: the column pass configuration, widened on lines of length >= GHOM_YSEG_MIN_N where
+// its segments would be shorter than GHOM_YSEG bytes (more columns per workgroup, up to 512
+// threads and 80 KiB of LDS).  Measured, float32: 256^3 y pass 0.217 -> 0.206 ms with 32
+// columns (256 B) instead of 16; 192^3 0.092 -> 0.099 ms, so shorter lines keep theirs.
+#ifndef GHOM_YSEG
+#define GHOM_YSEG 256
+#endif
+#ifndef GHOM_YSEG_MIN_N
+#define GHOM_YSEG_MIN_N 256
+#endif
+template <typename T, int A, int B> struct YCfg {
+  using Base = ColCfg<T, A, B>;
+  static constexpr int want = A * B >= GHOM_YSEG_MIN_N ? GHOM_YSEG / (int)sizeof(cx<T>) : 0;
+  static constexpr int wide = pow2_floor(cmax(1, cmin(want, cmin(512 / A, 80 * 1024 / (int)sizeof(cx<T>) / (A * B + B)))));
+  static constexpr int TC = Base::TC >= want || wide <= Base::TC ? Base::TC : wide;
+  static constexpr int NT = A * TC;
+  static constexpr int RS = A * TC + TC;
+  static constexpr int LDS = B * RS;
+};
+
 // z passes: LP pairs of real lines (9 components each) per workgroup.  LP is at least
 // GHOM_ZLP (or enough for ~256 threads on short lines), bounded by 1024 threads and an
 // LDS budget of 80 KB.
@@ -249,7 +269,7 @@ template <typename T, int A, int B, int DIR, bool NTS>
 __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw,
                                            const CGScalars* __restrict__ sc, int bx) {
   constexpr bool kNT = NTS;  // nontemporal streamed accesses
-  using Cfg = ColCfg<T, A, B>;
+  using Cfg = YCfg<T, A, B>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
   __shared__ cx<T> lds[Cfg::LDS];
@@ -1516,12 +1536,12 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
 // alpha_nparts > 0: block 0 of each problem first sets the CG step's alpha from that many
 // partials of the forward z pass
 template <typename T, int A, int B, int DIR, bool NTS>
-__global__ void __launch_bounds__((ColCfg<T, A, B>::NT))
+__global__ void __launch_bounds__((YCfg<T, A, B>::NT))
 ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl, int alpha_nparts) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   if (alpha_nparts > 0 && blockIdx.x == 0) {
-    cg_alpha_block<ColCfg<T, A, B>::NT>(d.sc, d.partials, alpha_nparts);
+    cg_alpha_block<YCfg<T, A, B>::NT>(d.sc, d.partials, alpha_nparts);
     __syncthreads();  // a breakdown (done = 1) is seen by every thread of the block below
   }
   ypass_body<T, A, B, DIR, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
