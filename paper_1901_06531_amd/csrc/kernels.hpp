@@ -159,25 +159,30 @@ template <typename T, int A, int B, int TCMAX = 64, int MAXT = 256> struct ColCf
   static constexpr int LDS = B * RS;
 };
 
-// y passes: the column pass configuration, widened on lines of length >= GHOM_YSEG_MIN_N where
-// its segments would be shorter than GHOM_YSEG bytes (more columns per workgroup, up to 512
-// threads and 80 KiB of LDS).  Measured, float32: 256^3 y pass 0.217 -> 0.206 ms with 32
-// columns (256 B) instead of 16; 192^3 0.092 -> 0.099 ms, so shorter lines keep theirs.
+// A column-pass configuration widened on lines of length >= MIN_N where its segments would be
+// shorter than SEG bytes (more columns per workgroup, up to 512 threads and 80 KiB of LDS).
+template <typename T, int A, int B, int MAXT, int SEG, int MIN_N> struct WideColCfg {
+  using Base = ColCfg<T, A, B, 64, MAXT>;
+  static constexpr int want = A * B >= MIN_N ? SEG / (int)sizeof(cx<T>) : 0;
+  static constexpr int lds_cap = 80 * 1024 / (int)sizeof(cx<T>) / (A * B + B);  // columns in 80 KiB
+  static constexpr int wide = pow2_floor(cmax(1, cmin(want, cmin(512 / A, lds_cap))));
+  static constexpr int TC = Base::TC >= want || wide <= Base::TC ? Base::TC : wide;
+  static constexpr int NT = A * TC;
+  static constexpr int RS = A * TC + TC;
+  static constexpr int LDS = B * RS;
+};
+
+// y passes: widened to 256-B segments on lines >= 256.  Measured, float32: 256^3 y pass 0.217
+// -> 0.206 ms with 32 columns instead of 16; 192^3 0.092 -> 0.099 ms, so shorter lines keep
+// theirs.  (The x pass gains nothing from it: its register-capped "rows" build, the fastest
+// at 256^3, runs 0.259 -> 0.264 ms with 32 columns.)
 #ifndef GHOM_YSEG
 #define GHOM_YSEG 256
 #endif
 #ifndef GHOM_YSEG_MIN_N
 #define GHOM_YSEG_MIN_N 256
 #endif
-template <typename T, int A, int B> struct YCfg {
-  using Base = ColCfg<T, A, B>;
-  static constexpr int want = A * B >= GHOM_YSEG_MIN_N ? GHOM_YSEG / (int)sizeof(cx<T>) : 0;
-  static constexpr int wide = pow2_floor(cmax(1, cmin(want, cmin(512 / A, 80 * 1024 / (int)sizeof(cx<T>) / (A * B + B)))));
-  static constexpr int TC = Base::TC >= want || wide <= Base::TC ? Base::TC : wide;
-  static constexpr int NT = A * TC;
-  static constexpr int RS = A * TC + TC;
-  static constexpr int LDS = B * RS;
-};
+template <typename T, int A, int B> using YCfg = WideColCfg<T, A, B, 256, GHOM_YSEG, GHOM_YSEG_MIN_N>;
 
 // z passes: LP pairs of real lines (9 components each) per workgroup.  LP is at least
 // GHOM_ZLP (or enough for ~256 threads on short lines), bounded by 1024 threads and an
