@@ -302,7 +302,7 @@ def main():
                     help="only run a plain 1 GiB device copy (5 times): the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     if args.paper_example:
