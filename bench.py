@@ -57,8 +57,11 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter runs, or None if the kernels changed."""
+def measured_traffic(kernel, shape):
+    """HBM bytes per launch from the committed counter runs (256^3 polycrystal), or None for
+    another grid or if the kernels changed since."""
+    if tuple(shape) != (256, 256, 256):
+        return None
     path = os.path.join(ROOT, "profiles", "polycrystal256_hbm_traffic.json")
     try:
         with open(path) as f:
@@ -351,7 +354,8 @@ def main():
         avg_s = ms / launches / 1e3
         achieved = per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, w["shape"]),
+                "kernel": name,
                 "avg_ms": round(ms / launches, 4), "bytes_per_launch": per_launch}
         log("kernel times (timed region): " + ", ".join("%s %.3f ms x%d" % (k, v[1] / v[0], v[0])
                                                         for k, v in sorted(op.items())))
