@@ -222,8 +222,8 @@ def cpu_baseline(w, seconds=15.0):
     dt = time.perf_counter() - t0
     N = int(np.prod(w["shape"]))
     return {"value": N * its / dt, "unit": "voxel-iters/s", "cores": go.WORKERS, "kind": "oracle",
-            "sample": "%d CG iteration(s) of the oracle's first Newton solve on the same %s workload "
-                      "(%.1f s)" % (its, w["name"], dt)}
+            "sample": "%d CG iteration(s) of the oracle's first Newton solve on %s, the %d^3 instance of "
+                      "the benchmark's workload generator (%.1f s)" % (its, w["name"], w["shape"][0], dt)}
 
 
 def run_paper_example(n, nsteps, precision_name):
