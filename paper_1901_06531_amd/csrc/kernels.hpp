@@ -1092,15 +1092,32 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
   const long long line0 = (long long)bx * (2 * LP);
   const int nzh = g.nzh;
   // phase 1: Z[k] = A[k] + i B[k] with Hermitian completion; Nyquist (even NZ) is zero
-  for (int t = threadIdx.x; t < 9 * LP * nzh; t += NT) {
-    const int ff = t / nzh, kz = t - ff * nzh;
-    const int c = ff / LP, pair = ff - c * LP;
-    const long long l0 = line0 + 2 * pair;
-    const cx<T> a = l0 < nlines ? ld_cx<kNT>(&args.H[c * g.Nh + l0 * nzh + kz]) : cx<T>{0, 0};
-    const cx<T> b = l0 + 1 < nlines ? ld_cx<kNT>(&args.H[c * g.Nh + (l0 + 1) * nzh + kz]) : cx<T>{0, 0};
-    lds[ff * R + kz] = a + mul_i<+1>(b);
-    if (kz > 0) lds[ff * R + NZ - kz] = conj(a) + mul_i<+1>(conj(b));
-    if ((NZ % 2 == 0) && kz == 0) lds[ff * R + NZ / 2] = cx<T>{0, 0};
+  // (all of a thread's spectrum loads are issued before its LDS stores: measured faster in
+  // every inverse pass, e.g. the float64 residual's 0.465 -> 0.414 ms at 256^3)
+  {
+    constexpr int IT1 = (9 * LP * (NZ / 2 + 1) + NT - 1) / NT;  // nzh <= NZ / 2 + 1
+    const int total = 9 * LP * nzh;
+    cx<T> av[IT1], bv[IT1];
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+      const int t = threadIdx.x + it * NT;
+      const int tt = t < total ? t : 0;
+      const int ff = tt / nzh, kz = tt - ff * nzh;
+      const int c = ff / LP, pair = ff - c * LP;
+      const long long l0 = line0 + 2 * pair;
+      av[it] = (t < total && l0 < nlines) ? ld_cx<kNT>(&args.H[c * g.Nh + l0 * nzh + kz]) : cx<T>{0, 0};
+      bv[it] = (t < total && l0 + 1 < nlines) ? ld_cx<kNT>(&args.H[c * g.Nh + (l0 + 1) * nzh + kz]) : cx<T>{0, 0};
+    }
+#pragma unroll
+    for (int it = 0; it < IT1; ++it) {
+      const int t = threadIdx.x + it * NT;
+      if (t >= total) break;
+      const int ff = t / nzh, kz = t - ff * nzh;
+      const cx<T> a = av[it], b = bv[it];
+      lds[ff * R + kz] = a + mul_i<+1>(b);
+      if (kz > 0) lds[ff * R + NZ - kz] = conj(a) + mul_i<+1>(conj(b));
+      if ((NZ % 2 == 0) && kz == 0) lds[ff * R + NZ / 2] = cx<T>{0, 0};
+    }
   }
   __syncthreads();
   constexpr int DIRZ = +1;
