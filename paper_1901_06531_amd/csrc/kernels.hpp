@@ -783,25 +783,12 @@ struct ZfwdArgs {
 // 0.578 ms, inverse 0.676 -> 0.664 ms; float64 CG passes forward (one chunk) 1.270 -> 1.173
 // ms, inverse (chunks of two: one chunk loses occupancy) 1.333 -> 1.308 ms; float64 Newton
 // update 0.998 -> 0.755 ms.  The residual pass (constitutive update fused) runs slower staged.
-#ifndef GHOM_ZPF_CG32
-#define GHOM_ZPF_CG32 1
-#endif
-#ifndef GHOM_ZPF_CG64
-#define GHOM_ZPF_CG64 1
-#endif
-#ifndef GHOM_ZPF_ZINV
-#define GHOM_ZPF_ZINV 1
-#endif
-#ifndef GHOM_ZPF_NEWTON
-#define GHOM_ZPF_NEWTON 1
-#endif
 #ifndef GHOM_ZPF_DEPTH64_FWD
 #define GHOM_ZPF_DEPTH64_FWD 8
 #endif
 #ifndef GHOM_ZPF_DEPTH64_INV
 #define GHOM_ZPF_DEPTH64_INV 2
 #endif
-template <typename T> constexpr bool zpf_cg() { return sizeof(T) == 4 ? GHOM_ZPF_CG32 != 0 : GHOM_ZPF_CG64 != 0; }
 // voxels per chunk of a staged CG loop of trip count it: all of them in float32, at most
 // GHOM_ZPF_DEPTH64_FWD / _INV in float64 (twice the registers per value)
 template <typename T, bool FWD> constexpr int zpf_depth(int it) {
@@ -924,7 +911,7 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   int bad = 0;
   const T beta = (CG && args.update_p == 1) ? (T)args.sc->beta : (T)0;
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
-  if constexpr (CG && zpf_cg<T>()) {
+  if constexpr (CG) {
     constexpr int SD = zpf_depth<T, true>((2 * LP * NZ + NT - 1) / NT);
     pkp = zfwd_cg_fill<T, LP, NT, NZ, R, MODE, TIN, SD, NTS>(g, args, line0, nlines, beta, ldsr);
   } else
@@ -937,7 +924,7 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
       if constexpr (MODE == Z_PLAIN) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) val[c] = (T)ld_s<kNT>(&args.in[c * g.N + vox]);
-      } else if constexpr (CONST) {
+      } else {  // fused residual: constitutive update
         double f[9], pv[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) f[c] = ld_s<kNT>(&args.F[c * g.N + vox]);
@@ -951,52 +938,6 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
           val[c] = (T)pv[c];
           cs[c] += f[c];
           cs[9 + c] += pv[c];
-        }
-      } else {
-        T d[9];
-        if (args.update_p == 2) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            const long long i = c * g.N + vox;
-            d[c] = (T)args.b[i];
-            args.r[i] = d[c];
-            args.p[i] = d[c];
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) d[c] = args.p[c * g.N + vox];
-          if (args.update_p == 1) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) {
-              const long long i = c * g.N + vox;
-              d[c] = args.r[i] + beta * d[c];
-              args.p[i] = d[c];
-            }
-          }
-        }
-        if constexpr (MODE == Z_NH) {
-          T st[kNHState];
-#pragma unroll
-          for (int k = 0; k < kNHState; ++k) st[k] = args.state[k * g.N + vox];
-          tangent_nh(st, d, val);
-        } else if constexpr (MODE == Z_SVK) {
-          T H[9];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) H[k] = args.state[k * g.N + vox];
-          const T sv = args.has_scale ? args.state[9 * g.N + vox] : (T)1;
-          tangent_svk(H, sv, args.C6 + 36 * args.phase[vox], d, val);
-        } else {
-          T H[9], S[6];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) H[k] = args.state[k * g.N + vox];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) S[k] = args.state[(9 + k) * g.N + vox];
-          const T sv = args.has_scale ? args.state[15 * g.N + vox] : (T)1;
-          tangent_visco(H, S, sv, args.C6 + 36 * args.phase[vox], d, val);
-        }
-        if (args.partials) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) pkp += (double)d[c] * (double)val[c];
         }
       }
     } else {
@@ -1073,8 +1014,8 @@ struct ZinvArgs {
   const TOUT* p;
   int first;                  // ZI_CG: first iteration (x is not read)
   double* F;                  // ZI_NEWTON
-  const TOUT* dot_with;       // ZI_PLAIN, nullable: partial sum of out . dot_with per block
-  double* partials;           // ZI_CG / dot_with: one per block; ZI_NEWTON: 10 columns
+  int self_dot;               // ZI_PLAIN: partial sum of out . out per block
+  double* partials;           // ZI_CG / self_dot: one per block; ZI_NEWTON: 10 columns
   int pstride;                // ZI_NEWTON: column k of block bx at partials[k * pstride + bx]
   const cx<T>* tw;
   const CGScalars* sc;        // early exit (nullable)
@@ -1150,7 +1091,7 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
   for (int c = 0; c < (ZM == ZI_NEWTON ? 9 : 1); ++c) fs[c] = 0.0;
   const TOUT alpha = ZM == ZI_CG ? (TOUT)args.sc->alpha : (TOUT)0;
-  if constexpr ((ZM == ZI_CG && zpf_cg<TOUT>() && GHOM_ZPF_ZINV) || (ZM == ZI_NEWTON && GHOM_ZPF_NEWTON)) {
+  if constexpr (ZM == ZI_CG || ZM == ZI_NEWTON) {
     // every load of a chunk of this thread's voxels first, then the updates and stores (the
     // CG update in chunks of zpf_depth voxels, the Newton update all at once)
     constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
@@ -1232,28 +1173,12 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
     if (line >= nlines) continue;
     const long long vox = line * NZ + z;
     const int pair = lp >> 1, part = lp & 1;
-    double n2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
-      const long long i = c * g.N + vox;
-      if constexpr (ZM == ZI_CG) {
-        const TOUT xv = (args.first ? (TOUT)0 : args.x[i]) + alpha * args.p[i];
-        const TOUT rv = args.r[i] - alpha * o;
-        args.x[i] = xv;
-        args.r[i] = rv;
-        acc += (double)rv * (double)rv;
-      } else if constexpr (ZM == ZI_NEWTON) {
-        const double fn = args.F[i] + (double)o;
-        args.F[i] = fn;
-        n2 += (double)o * (double)o;
-        fs[c] += fn;
-      } else {
-        st_s<kNT>(&args.out[i], o);
-        if (args.dot_with) acc += (double)o * (double)args.dot_with[i];
-      }
+      st_s<kNT>(&args.out[c * g.N + vox], o);
+      if (args.self_dot) acc += (double)o * (double)o;
     }
-    if constexpr (ZM == ZI_NEWTON) acc = fmax(acc, n2);
   }
   if constexpr (ZM == ZI_NEWTON) {
     __shared__ double sh[10 * ((NT + 63) / 64)];
@@ -1262,7 +1187,7 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
     for (int c = 0; c < 9; ++c) v[1 + c] = fs[c];
     block_reduce_cols<NT, 10, 1>(v, sh, [&](int k, double t) { args.partials[(long long)k * args.pstride + bx] = t; });
-  } else if (ZM == ZI_CG || args.dot_with) {
+  } else if (ZM == ZI_CG || args.self_dot) {
     const double s = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) args.partials[bx] = s;
   }
@@ -1621,7 +1546,7 @@ zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
     a.out = (role == ROLE_RESID || role == ROLE_ADJ)
                 ? reinterpret_cast<TOUT*>(d.b)
                 : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
-    a.dot_with = (role == ROLE_RESID || role == ROLE_ADJ) ? a.out : nullptr;
+    a.self_dot = role == ROLE_RESID || role == ROLE_ADJ;
   }
   zinv_body<T, A, B, TOUT, ZM, NTS>(d.g, a, blockIdx.x);
 }
