@@ -132,6 +132,60 @@ def apply_projection(field9: np.ndarray, mask, lengths=(1.0, 1.0, 1.0)) -> np.nd
 
 
 # --------------------------------------------------------------------------------------
+# Rotation gauge under full stress control (Sec. 2.2; a reading, the paper is silent)
+# --------------------------------------------------------------------------------------
+
+def rotation_gauge_axis(mask, target):
+    """Axis a of the rotation gauge, or None when the gauge does not apply.
+
+    Under full stress control (every component stress-controlled, eq. 19) F is fixed only
+    up to the rigid rotations Q with Q P-bar = P-bar: all three rotations when P-bar = 0,
+    the rotation about a when P-bar = p e_a (x) e_a.  The gauge applies when the mask is
+    all ones and every target row of the history is a multiple of e_a (x) e_a for one axis
+    a (the zero history takes a = 0).
+    """
+    m = np.asarray(mask).reshape(9)
+    if not np.all(m == 1):
+        return None
+    T = np.asarray(target, dtype=float).reshape(-1, 9)
+    for a in range(3):
+        off = [c for c in range(9) if c != 4 * a]
+        if np.all(T[:, off] == 0.0):
+            return a
+    return None
+
+
+def rotation_gauge_components(a):
+    """Components held fixed by the gauge of axis a: with (a, b, c) in cyclic order, the
+    entries F_ba, F_ca and F_cb (the strict lower triangle in the order a, b, c).
+
+    Why this is the same problem: for periodic compatible F and divergence-free P the mean
+    of P F^T equals <P> <F>^T (the fluctuation term integrates to zero), and P F^T is
+    symmetric at every voxel for an objective law, so <P> <F>^T is symmetric at
+    equilibrium.  With <F>_ba = <F>_ca = <F>_cb = 0 and the six other stress components at
+    p e_a (x) e_a, that symmetry forces <P>_ba = <P>_ca = <P>_cb = 0: the released
+    components still meet the target.  Among the rotated solutions Q F (Q P-bar = P-bar)
+    exactly one has the three entries zero, so the gauge removes the null space of the
+    rotations without changing the rotation invariants (<P>, <F>^T <F>, F^T F per voxel).
+    """
+    b, c = (a + 1) % 3, (a + 2) % 3
+    return [3 * b + a, 3 * c + a, 3 * c + b]
+
+
+def effective_mask(mask, target, gauge=True):
+    """The control mask the solver uses: ``mask`` with the rotation gauge applied (its
+    three components become deformation-controlled, held at their current value because
+    their target entries are zero)."""
+    m = np.asarray(mask, dtype=float).reshape(9).copy()
+    if not gauge or target is None:
+        return m
+    a = rotation_gauge_axis(m, target)
+    if a is not None:
+        m[rotation_gauge_components(a)] = 0.0
+    return m
+
+
+# --------------------------------------------------------------------------------------
 # Hyperelastic materials (Sec. 3.1 Saint Venant-Kirchhoff; compressible neo-Hookean)
 # All functions act on voxel-first arrays of 3x3 matrices, shape (M, 3, 3).
 # --------------------------------------------------------------------------------------
@@ -282,7 +336,9 @@ class Oracle:
         self.kind = None
         self.phase = None
         self.scale = np.ones(self.N)
-        self.mask = np.zeros(9)
+        self.mask = np.zeros(9)       # the mask the solver uses (rotation gauge applied)
+        self.user_mask = np.zeros(9)  # the mask as set
+        self.gauge = True
         self.target = None
         self.newton_tol = 1e-6
         self.cg_tol = 1e-8
@@ -292,8 +348,17 @@ class Oracle:
         self.k = 0
         self.dt = 1.0
         self.cg_breakdowns = 0
+        self.cg_stalls = 0
+        self.cg_stall_window = 20
         self.F = np.tile(EYE9[:, None], (1, self.N)).reshape((9,) + self.shape)
         self.history: list[StepRecord] = []
+
+    @property
+    def gauge_axis(self):
+        """Axis of the rotation gauge in use, or None (see rotation_gauge_axis)."""
+        if not self.gauge or self.target is None:
+            return None
+        return rotation_gauge_axis(self.user_mask, self.target)
 
     # ---- set-up ---------------------------------------------------------------------
     def set_material_neohookean(self, phase, mu, lam):
@@ -330,12 +395,19 @@ class Oracle:
         self.scale = np.ones(self.N) if s is None else np.asarray(s, float).reshape(-1).copy()
 
     def set_control(self, mask):
-        self.mask = np.asarray(mask, dtype=float).reshape(9).copy()
+        self.user_mask = np.asarray(mask, dtype=float).reshape(9).copy()
+        self.mask = effective_mask(self.user_mask, self.target, self.gauge)
 
     def set_history(self, target):
         """target[k-1] holds, for increment k, P-bar on stress-controlled and F-bar on
         deformation-controlled components (Sec. 2.3, eq. 21)."""
         self.target = np.asarray(target, dtype=float).reshape(-1, 9).copy()
+        self.mask = effective_mask(self.user_mask, self.target, self.gauge)
+
+    def set_rotation_gauge(self, on):
+        """Turn the rotation gauge of full stress control on (default) or off."""
+        self.gauge = bool(on)
+        self.mask = effective_mask(self.user_mask, self.target, self.gauge)
 
     def set_tolerances(self, newton_tol, cg_tol, cg_forcing=0.0, max_newton=50, max_cg=5000):
         self.newton_tol, self.cg_tol, self.cg_forcing = float(newton_tol), float(cg_tol), float(cg_forcing)
@@ -409,6 +481,14 @@ class Oracle:
         """Voxel-averaged L2 norm: sqrt( (1/N) sum_x |v(x)|^2 ) (Sec. 4)."""
         return math.sqrt(float(np.vdot(v9, v9)) / self.N)
 
+    @staticmethod
+    def newton_criterion(dF9, Favg9) -> float:
+        """Newton stop quantity of Sec. 4: the largest correction of the deformation gradient
+        over the voxels relative to the averaged one, max_x |dF(x)| / |<F>| (Frobenius
+        norms)."""
+        per_voxel = np.sqrt(np.sum(np.asarray(dF9, float).reshape(9, -1) ** 2, axis=0))
+        return float(np.max(per_voxel)) / float(np.linalg.norm(np.asarray(Favg9, float).reshape(9)))
+
     def conjugate_gradient(self, b9, F9=None):
         """Solve A dF = b by plain conjugate gradients from dF = 0 (Sec. 2.1).
 
@@ -417,19 +497,29 @@ class Oracle:
 
         Breakdown (p.Ap <= 0 or not finite): at the first iteration nothing can be done and
         BreakdownError is raised; later, the iterate reached so far is returned and the
-        count ``self.cg_breakdowns`` is raised by one.  Under full stress control the rigid
-        rotations that leave P-bar unchanged make A singular (slightly indefinite away from
-        equilibrium); CG then stalls at round-off level and the Newton loop carries on.
+        count ``self.cg_breakdowns`` is raised by one.  Under full stress control without
+        the rotation gauge the rigid rotations that leave P-bar unchanged make A singular
+        (slightly indefinite away from equilibrium); CG then stalls at round-off level and
+        the Newton loop carries on.
+
+        Stall (a reading; the paper names no safeguard): when r.r has not gone below its
+        smallest value in the solve for ``cg_stall_window`` iterations in a row, the
+        residual has a floor above the threshold (a right-hand side the operator cannot
+        reach); the iterate is returned and ``self.cg_stalls`` is raised by one.
         """
         x = np.zeros_like(b9)
         r = b9.copy()
         p = r.copy()
         rr = float(np.vdot(r, r))
         tol = max(self.cg_tol, self.cg_forcing * math.sqrt(rr / self.N))
+        best, since = rr, 0
         it = 0
         while math.sqrt(rr / self.N) > tol:
             if it >= self.max_cg:
                 raise NotConvergedError("CG reached max_cg=%d" % self.max_cg)
+            if since >= self.cg_stall_window:
+                self.cg_stalls += 1
+                break
             Ap = self.apply_operator(p, F9)
             pAp = float(np.vdot(p, Ap))
             if not (pAp > 0.0 and math.isfinite(pAp)):
@@ -445,6 +535,10 @@ class Oracle:
             p = r + beta * p
             rr = rr_new
             it += 1
+            if rr < best:
+                best, since = rr, 0
+            else:
+                since += 1
         return x, it
 
     def averages(self, F9=None, P9=None):
@@ -514,8 +608,7 @@ class Oracle:
             per.append(its)
             cg_total += its
             self.F = self.F + dF
-            Favg = self.F.reshape(9, -1).mean(axis=1)
-            crit = float(np.max(np.sqrt(np.sum(dF.reshape(9, -1) ** 2, axis=0)))) / float(np.linalg.norm(Favg))
+            crit = self.newton_criterion(dF, self.F.reshape(9, -1).mean(axis=1))
             if crit < self.newton_tol:
                 converged = True
                 break

@@ -334,3 +334,106 @@ def test_inverted_deformation_is_a_domain_error():
             F_end.reshape(1, 9))
     with pytest.raises(go.DomainError):
         o.step()
+
+
+# ---------------------------------------------------------------- stop rules (Sec. 4) --
+
+def test_voxel_averaged_l2_norm():
+    """rms is the voxel-averaged L2 norm of Sec. 4: sqrt of the mean over voxels of the
+    squared Frobenius norm.  A uniform field of norm a gives a; a single voxel of norm a
+    gives a / sqrt(N) (the mean of the norms would give a / N, the plain 2-norm a)."""
+    shape = (4, 6, 5)
+    N = 120
+    o = go.Oracle(shape)
+    rng = np.random.default_rng(7)
+    t = rng.standard_normal(9)
+    a = 0.37
+    t *= a / np.linalg.norm(t)
+    uniform = np.broadcast_to(t[:, None, None, None], (9,) + shape).copy()
+    assert abs(o.rms(uniform) - a) < 1e-15
+    single = np.zeros((9,) + shape)
+    single[:, 2, 3, 1] = t
+    assert abs(o.rms(single) - a / np.sqrt(N)) < 1e-16
+    # two voxels of norms 3 and 4: sqrt((9 + 16) / N)
+    two = np.zeros((9,) + shape)
+    two[0, 0, 0, 0], two[4, 1, 2, 3] = 3.0, 4.0
+    assert abs(o.rms(two) - 5.0 / np.sqrt(N)) < 1e-15
+
+
+def test_newton_criterion():
+    """max over voxels of |dF(x)| divided by |<F>| (Frobenius norms, Sec. 4)."""
+    shape = (3, 4, 5)
+    dF = np.zeros((9,) + shape)
+    dF[1, 2, 3, 4] = 3.0
+    dF[5, 2, 3, 4] = 4.0       # that voxel has norm 5
+    dF[0, 0, 0, 0] = 4.5       # a smaller one elsewhere
+    I9 = go.EYE9
+    assert abs(go.Oracle.newton_criterion(dF, I9) - 5.0 / np.sqrt(3.0)) < 1e-15
+    assert abs(go.Oracle.newton_criterion(dF, 2.0 * I9) - 2.5 / np.sqrt(3.0)) < 1e-15
+    Fbar = np.array([1.1, 0.2, 0, 0, 0.9, 0, 0.3, 0, 1.0])
+    assert abs(go.Oracle.newton_criterion(dF, Fbar) - 5.0 / np.linalg.norm(Fbar)) < 1e-15
+    # a uniform correction: its norm over |<F>|
+    u = np.broadcast_to(np.arange(9.0)[:, None, None, None], (9,) + shape)
+    assert abs(go.Oracle.newton_criterion(u, I9) - np.sqrt(204.0) / np.sqrt(3.0)) < 1e-13
+
+
+def test_cg_stops_on_the_voxel_averaged_residual():
+    """The CG solve returns once rms(b - A x) is below the threshold and not before: the
+    true residual of the returned iterate is below cg_tol, the iterate of one iteration
+    less is above it."""
+    shape = (8, 8, 8)
+    # mixed control (the paper's case (1)): the rotations are fixed, A is positive definite
+    o = _nh(shape, _two_phase(shape, 3), [1.0, 10.0], [2.0, 20.0], CASE1,
+            synth.history_mixed(CASE1, np.diag([1.05, 1, 1]).reshape(9), 1))
+    o.F = o.F + 0.02 * np.random.default_rng(1).standard_normal(o.F.shape)
+    b = o.residual(o.stress(), np.zeros(9))
+    o.cg_tol = 1e-3 * o.rms(b)
+    x, its = o.conjugate_gradient(b)
+    assert its >= 2 and o.cg_breakdowns == 0
+    assert o.rms(b - o.apply_operator(x)) <= o.cg_tol * (1 + 1e-8)
+    o.max_cg = its - 1
+    with pytest.raises(go.NotConvergedError):
+        o.conjugate_gradient(b)
+
+
+def test_newton_records_the_criterion_of_its_last_correction():
+    shape = (8, 8, 8)
+    o = _nh(shape, _two_phase(shape, 4), [1.0, 10.0], [2.0, 20.0], synth.mask_full_stress(),
+            synth.history_stress_ramp(np.diag([0.05, 0, 0]).reshape(9), 1), ntol=1e-6, ctol=1e-9)
+    F0 = o.F.copy()
+    o.max_newton = 1
+    with pytest.raises(go.NotConvergedError):
+        o.step()
+    dF = o.F - F0
+    expect = go.Oracle.newton_criterion(dF, o.F.reshape(9, -1).mean(axis=1))
+    o2 = _nh(shape, _two_phase(shape, 4), [1.0, 10.0], [2.0, 20.0], synth.mask_full_stress(),
+             synth.history_stress_ramp(np.diag([0.05, 0, 0]).reshape(9), 1), ntol=expect * 1.0000001, ctol=1e-9)
+    rec = o2.step()
+    assert rec.newton_iters == 1 and abs(rec.crit - expect) < 1e-15 * max(1.0, expect)
+
+
+def test_cg_stall_returns_the_iterate():
+    """An operator whose output carries a relative error of 1e-6 (a residual floor) with a
+    threshold far below that floor: the solve stops after the stall window instead of
+    running to max_cg, returns its iterate and counts the stall."""
+    shape = (6, 6, 6)
+    o = _nh(shape, _two_phase(shape, 5), [1.0, 10.0], [2.0, 20.0], CASE1,
+            synth.history_mixed(CASE1, np.diag([1.05, 1, 1]).reshape(9), 1))
+    exact = o.apply_operator
+    rng = np.random.default_rng(11)
+
+    def noisy(v, F9=None):
+        out = exact(v, F9)
+        return out + 1e-6 * np.linalg.norm(out) / np.sqrt(out.size) * rng.standard_normal(out.shape)
+
+    o.apply_operator = noisy
+    b = o.residual(o.stress(), np.zeros(9)) + go.apply_projection(
+        0.01 * np.random.default_rng(2).standard_normal(o.F.shape), o.mask)
+    o.cg_tol = 1e-12 * o.rms(b)
+    o.max_cg = 1000
+    x, its = o.conjugate_gradient(b)
+    assert o.cg_stalls == 1 and o.cg_breakdowns == 0
+    assert o.cg_stall_window < its < 200
+    # the iterate is a useful one: the true residual is down by two orders at least (the
+    # noise of every operator output accumulates in the recursive residual)
+    assert o.rms(b - exact(x)) < 1e-2 * o.rms(b)
