@@ -8,7 +8,10 @@ CG 1e-8).  A step is one load increment: the shift of the prescribed means, then
 
 value = N * (CG iterations in the timed increments) / (wall time of those increments), the
 whole-job throughput with every input resident in HBM.  Prints ONE JSON line on stdout;
-progress goes to stderr.
+progress goes to stderr.  The default run (2 warm-up + 38 timed increments) covers the whole
+40-increment cycle, both stress-free crossings included; more increments than that cycle the
+periodic history again.  An increment that fails is recorded in the JSON (status, message)
+and stays in the timed region.
 """
 
 import argparse
@@ -74,11 +77,19 @@ def measured_traffic(kernel, shape):
     return k["read_bytes"] + k["write_bytes"]
 
 
+def cycled_history(target, total):
+    """The periodic load history repeated until it holds `total` increments."""
+    reps = -(-total // len(target))
+    return np.tile(target, (reps, 1))[:max(total, len(target))]
+
+
 def run_gpu(w, precision, steps, warmup, profile):
     from paper_1901_06531_amd import ghom
 
     s = ghom.Solver(w["shape"], precision=precision)
     s.setup(w)
+    s.set_history(cycled_history(w["target"], steps + warmup))
+    gauge = s.control()[1]
     xproj = {"f64": s.get_option(ghom.OPT_XPROJ_F64), "f32": s.get_option(ghom.OPT_XPROJ_F32)}
     # both precisions stop CG at max(1e-8, 1e-5 |b|): the float32 CG needs the relative
     # floor, and the float64 run uses the same rule so that the two are compared fairly
@@ -89,10 +100,33 @@ def run_gpu(w, precision, steps, warmup, profile):
     if profile and warmup:
         s.profile_reset()
         s.set_profiling(True)
+    failures = []
+
+    def one(k, what):
+        info = s.step(check=False)
+        if info["status"] != 0:
+            failures.append({"increment": k, "phase": what, "status": info["status"], "error": info["error"],
+                             "newton_iters": info["newton_iters"], "cg_iters": info["cg_iters_total"]})
+            log("  %s increment %d FAILED: %s" % (what, k, info["error"]))
+            if info["status"] != ghom.STATUS_CODE["ENOTCONVERGED"]:
+                # the increment was not advanced (ESINGULAR, EDOMAIN): retry it in halves
+                try:
+                    info2 = s.step_adaptive(max_cuts=8, grow_below=2)
+                except ghom.GhomError as ex:
+                    failures[-1]["recovered_by"] = "nothing: step_adaptive failed too (%s)" % ex
+                    info["stuck"] = True
+                    return info
+                failures[-1]["recovered_by"] = "step_adaptive: %d substeps, %d cuts" % (info2["substeps"],
+                                                                                       info2["cuts"])
+                for key in ("newton_iters", "cg_iters_total", "t_cg_ms", "t_total_ms", "cg_stalls"):
+                    info[key] += info2[key]
+        log("  %s increment %d: newton %d cg %d stalls %d  %.1f ms" % (
+            what, k, info["newton_iters"], info["cg_iters_total"], info["cg_stalls"], info["t_total_ms"]))
+        return info
+
     for i in range(warmup):
-        info = s.step()
-        log("  warmup increment %d: newton %d cg %d  %.1f ms" % (i + 1, info["newton_iters"], info["cg_iters_total"],
-                                                                 info["t_total_ms"]))
+        if one(i + 1, "warmup").get("stuck"):
+            raise RuntimeError("warm-up increment %d could not be advanced: %s" % (i + 1, failures[-1]))
     warm_prof = {}
     if profile and warmup:
         warm_prof = s.profile()
@@ -106,10 +140,9 @@ def run_gpu(w, precision, steps, warmup, profile):
     infos = []
     t0 = time.perf_counter()
     for i in range(steps):
-        info = s.step()
-        infos.append(info)
-        log("  timed increment %d: newton %d cg %d  %.1f ms" % (warmup + i + 1, info["newton_iters"],
-                                                                info["cg_iters_total"], info["t_total_ms"]))
+        infos.append(one(warmup + i + 1, "timed"))
+        if infos[-1].get("stuck"):
+            break  # the same increment would fail again; the partial region is reported
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = s.profile() if profile else {}
@@ -123,11 +156,18 @@ def run_gpu(w, precision, steps, warmup, profile):
     N = int(np.prod(w["shape"]))
     return {
         "voxel_iters_per_s": N * cg / wall,
-        "ms_per_increment": 1e3 * wall / steps,
+        "ms_per_increment": 1e3 * wall / len(infos),
+        "increments_timed": len(infos),
         "newton_step_ms": 1e3 * wall / max(newton, 1),
         "cg_ms_per_iter": sum(i["t_cg_ms"] for i in infos) / max(cg, 1),
         "cg_iters": cg,
         "newton_iters": newton,
+        "cg_stalls": sum(i["cg_stalls"] for i in infos),
+        "cg_breakdowns": sum(i["cg_breakdowns"] for i in infos),
+        "newton_per_increment": [i["newton_iters"] for i in infos],
+        "cg_per_increment": [i["cg_iters_total"] for i in infos],
+        "failures": failures,
+        "rotation_gauge_axis": gauge,
         "F11": float(F[0]),
         "P11": float(P[0]),
         "xproj_variant": xproj,
@@ -291,8 +331,8 @@ def run_paper_example(n, nsteps, precision_name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=38)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -386,18 +426,26 @@ def main():
         "dtype": "f32/f64-split",
         "data": "synthetic",
         "config": {"workload": w["name"], "grid": list(w["shape"]), "grains": 512, "material": "svk-cubic",
-                   "control": "full stress, P11 triangle +-0.02 over 40 increments",
+                   "control": "full stress, P11 triangle +-0.02 over 40 increments (cycled)",
+                   "increments": [args.warmup + 1, args.warmup + args.steps],
                    "step": "one load increment", "precision": "fp32-split",
                    "newton_tol": w["newton_tol"], "cg_tol": w["cg_tol"], "cg_forcing": CG_FORCING},
         "newton_step_ms": round(split["newton_step_ms"], 3),
         "cg_ms_per_iter": round(split["cg_ms_per_iter"], 4),
         "cg_iters": split["cg_iters"],
         "newton_iters": split["newton_iters"],
+        "newton_per_increment": split["newton_per_increment"],
+        "cg_per_increment": split["cg_per_increment"],
+        "cg_stalls": split["cg_stalls"],
+        "cg_breakdowns": split["cg_breakdowns"],
+        "failures": split["failures"],
+        "rotation_gauge_axis": split["rotation_gauge_axis"],
         "xproj_variant": split["xproj_variant"],
         "fp64": None if fp64 is None else {
             "value": round(fp64["voxel_iters_per_s"], 1), "ms_per_step": round(fp64["ms_per_increment"], 3),
             "newton_step_ms": round(fp64["newton_step_ms"], 3), "cg_ms_per_iter": round(fp64["cg_ms_per_iter"], 4),
             "cg_iters": fp64["cg_iters"], "newton_iters": fp64["newton_iters"],
+            "cg_stalls": fp64["cg_stalls"], "failures": fp64["failures"],
             "split_vs_fp64_F11_diff": abs(fp64["F11"] - split["F11"])},
         "batch": batch,
         "roofline": roof,

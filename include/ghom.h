@@ -69,6 +69,10 @@ typedef struct {
   double res_rms;      /* voxel-averaged L2 norm of the last Newton residual               */
   double t_total_ms;   /* wall time of the call                                            */
   double t_cg_ms;      /* time inside the CG loops                                         */
+  int cg_stalls;       /* CG solves stopped because r.r found no new minimum in 20
+                          iterations (a residual floor above the threshold); Newton goes on
+                          with the iterate                                                  */
+  int reserved;
 } ghom_step_info;
 
 /* Creates a context for an nx x ny x nz voxel grid of the periodic cell of edge lengths
@@ -125,8 +129,25 @@ int ghom_set_time_step(ghom_ctx *ctx, double dt);
  * values; NULL restores s = 1).  Used by ghom_adjoint_grad_scale. */
 int ghom_set_stiffness_scale(ghom_ctx *ctx, const double *s);
 
-/* Control mask of eq. (22) (host, 9 bytes, see above). */
+/* Control mask of eq. (22) (host, 9 bytes, see above).
+ *
+ * Rotation gauge of full stress control (GHOM_OPT_ROTATION_GAUGE, on by default): with every
+ * component stress-controlled (eq. 19) the deformation gradient is fixed only up to the
+ * rigid rotations that leave the prescribed stress unchanged (P(QF) = Q P(F)): all three at a
+ * zero target, where the Newton system becomes singular, and the rotation about e_a under a
+ * uniaxial target p e_a (x) e_a.  When the mask is all ones and every row of the history is a
+ * multiple of e_a (x) e_a for one axis a, the solver holds the entries F_ba, F_ca and F_cb of
+ * <F> ((a, b, c) in cyclic order; zero from F = I) in place of the stress components ba, ca,
+ * cb.  At equilibrium <P> <F>^T is symmetric (the average of P F^T over a periodic cell with
+ * compatible F and divergence-free P, and P F^T is symmetric at each voxel), which with those
+ * three entries at zero forces the three released stress components to their target 0: the
+ * solution is the full stress one with its rotation fixed.  Any other mask or history is
+ * solved as set.  ghom_get_control reports the mask in use. */
 int ghom_set_control(ghom_ctx *ctx, const uint8_t mask[9]);
+
+/* The mask the solver uses (host, 9 bytes; nullable) and the axis of the rotation gauge
+ * (0..2, or -1 when it does not apply; nullable).  GHOM_ESTATE before ghom_set_control. */
+int ghom_get_control(ghom_ctx *ctx, uint8_t mask_out[9], int *gauge_axis);
 
 /* Load history (host, nsteps x 9): row k-1 holds, for increment k, the prescribed
  * P-bar on stress-controlled and F-bar on deformation-controlled components (eq. 21).
@@ -169,19 +190,30 @@ int ghom_step_adaptive(ghom_ctx *ctx, int max_cuts, int grow_below, ghom_step_in
  * (e.g. after ghom_set_stiffness_scale or ghom_load_state).  info as in ghom_step. */
 int ghom_resolve(ghom_ctx *ctx, ghom_step_info *info);
 
-/* Voxel averages <F> and <P> of the current state (host, 9 values each, float64). */
+/* Voxel averages <F> and <P> of the current state (host, 9 values each, float64): the
+ * macroscopic deformation gradient and first Piola-Kirchhoff stress, F-bar and P-bar of
+ * Sec. 2.1-2.3 (the mean of a field equals its zero-frequency Fourier coefficient, Sec. 2.2),
+ * whose histories are the paper's macroscopic response curves (Sec. 3.1 Fig. 1, Sec. 3.2
+ * Fig. 2).  Reduced in float64 in a fixed order (the same bits on every run). */
 int ghom_get_averages(ghom_ctx *ctx, double Fbar[9], double Pbar[9]);
 
-/* Copies field `which` (GHOM_FIELD_F or GHOM_FIELD_P, float64, 9 x N) to host memory. */
+/* Copies field `which` (GHOM_FIELD_F or GHOM_FIELD_P, float64, 9 x N, layout above) to host
+ * memory: the microscopic deformation gradient F(x) and stress P(F(x)) of Sec. 2.1 at the
+ * current state (the unknown of eq. 3-5 and its stress).  GHOM_EINVAL for another `which`. */
 int ghom_get_field(ghom_ctx *ctx, int which, double *host_out);
 
-/* Same into caller-owned device memory (float64, 9 x N). */
+/* Same into caller-owned device memory (float64, 9 x N): waits for the context's stream,
+ * then copies; returns when the copy has finished. */
 int ghom_get_field_device(ghom_ctx *ctx, int which, double *dev_out);
 
-/* Current deformation gradient (host, 9 x N) and increment index. */
+/* Current deformation gradient (host, 9 x N) and increment index: the state a load
+ * increment of Sec. 2.1 starts from (eq. 5: F of increment k+1 is sought from the converged F
+ * of increment k), so that a history can be resumed or an increment repeated. */
 int ghom_save_state(ghom_ctx *ctx, double *F_out, int *step_out);
 
-/* Sets the deformation gradient (host, 9 x N) and the increment index (0..nsteps). */
+/* Sets the deformation gradient (host, 9 x N) and the increment index (0..nsteps) -- the
+ * converged state of increment `step`, from which the next ghom_step starts (Sec. 2.1).
+ * GHOM_EINVAL for a step out of range. */
 int ghom_load_state(ghom_ctx *ctx, const double *F_in, int step);
 
 /* Adjoint gradient of J = a : <F> with respect to s(x) at the current (converged) state:
@@ -223,12 +255,15 @@ enum {
                               converged F and starting internal variables on the device
                               ((9 + 12) x N float64 each), as ghom_adjoint_grad_scale needs;
                               0: keep none (and drop those kept) */
-  GHOM_OPT_STREAM_NT = 6   /* 1: the transform passes load and store fields and spectra with
+  GHOM_OPT_STREAM_NT = 6,  /* 1: the transform passes load and store fields and spectra with
                               the nontemporal hint (no reuse expected in the last-level cache);
                               0: ordinary cached accesses.  Set at creation to 1 when one CG
                               iteration of all problems together touches more than 256 MB.
                               Passes along transform lines of length >= 128 always stream.
                               Results are the same either way. */
+  GHOM_OPT_ROTATION_GAUGE = 7 /* 1 (default): the rotation gauge of full stress control (see
+                              ghom_set_control); 0: the mask exactly as set.  Takes effect at
+                              the next solve. */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the fastest variant by timing

@@ -20,6 +20,7 @@
 
 #include "../../include/ghom.h"
 #include "kernels.hpp"
+#include "control.hpp"
 #include "substep.hpp"
 
 using namespace ghom;
@@ -69,8 +70,10 @@ struct Prob {
   int cls = -1;
   int kind = 0;
   int nphase = 0;
-  uint8_t mask[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  uint8_t mask[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};       // the mask the solver uses
+  uint8_t user_mask[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // the mask as set
   bool mask_set = false;
+  int gauge_axis = -1;  // axis of the rotation gauge of full stress control, or -1
   std::vector<double> target;
   int nsteps = 0;
   int k = 0;
@@ -126,6 +129,7 @@ struct Engine {
   bool stream_nt = false;  // nontemporal builds of the short-line pass kernels (set at creation)
   bool graphs = false;  // replay captured HIP graphs of CG iterations (not while profiling)
   bool checkpoints = false;  // keep per-increment states of path-dependent laws (adjoint)
+  bool rot_gauge = true;     // rotation gauge of full stress control (control.hpp)
   std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, first-iteration flag, iterations
   bool prof = false;
   std::string prof_only;  // time only launches of this name (empty: all)
@@ -605,7 +609,7 @@ void cg_solve(Engine& e, double* t_ms) {
   bool zeroed = false;
   for (auto& c : e.C)
     for (int p : c.probs)
-      if (e.hdesc[p].active && e.host_sc[p].it == 0 && e.host_sc[p].status == 1) {
+      if (e.hdesc[p].active && e.host_sc[p].it == 0 && e.host_sc[p].status == CG_CONVERGED) {
         const long long nd = (9LL * c.g.N * (long long)sizeof(T) + 7) / 8;  // arena buffers are padded
         hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, nd, reinterpret_cast<double*>(e.hdesc[p].x));
         HIPCALL(hipGetLastError());
@@ -719,7 +723,7 @@ void newton(Engine& e, const std::vector<int>& set) {
       q.info.t_cg_ms += tcg;
       const CGScalars& s = e.host_sc[p];
       q.info.cg_iters_total += s.it;
-      if (s.status == 2) {
+      if (s.status == CG_BREAKDOWN) {
         if (s.it == 0) {
           q.status = GHOM_ESINGULAR;
           q.msg = "CG breakdown (p.Ap <= 0) at its first iteration";
@@ -727,7 +731,9 @@ void newton(Engine& e, const std::vector<int>& set) {
         } else {
           q.info.cg_breakdowns += 1;
         }
-      } else if (s.status == 3) {
+      } else if (s.status == CG_STALLED) {
+        q.info.cg_stalls += 1;  // Newton continues with the iterate
+      } else if (s.status == CG_CAP) {
         q.status = GHOM_ENOTCONVERGED;
         q.msg = "CG reached max_cg";
         q.running = false;
@@ -777,6 +783,22 @@ void newton(Engine& e, const std::vector<int>& set) {
     e.P[p].info.t_total_ms = ms;
     e.P[p].info.status = e.P[p].status;
   }
+}
+
+// The mask problem p is solved with: the mask as set, with the rotation gauge of full
+// stress control applied when it is on and the history is uniaxial (control.hpp); mirrored
+// into the descriptor.
+void apply_control(Engine& e, int p) {
+  Prob& q = e.P[p];
+  if (!q.mask_set) return;
+  uint8_t m[9];
+  q.gauge_axis = effective_mask(q.user_mask, q.target.empty() ? nullptr : q.target.data(), q.nsteps, e.rot_gauge, m);
+  unsigned bits = 0;
+  for (int i = 0; i < 9; ++i) {
+    q.mask[i] = m[i];
+    if (m[i]) bits |= 1u << i;
+  }
+  e.hdesc[p].mask = bits;
 }
 
 // Prescribed values of increment k (row k-1 of the history); increment 0 is F = I, P = 0.
@@ -1387,12 +1409,9 @@ int ghom_set_control(ghom_ctx* c, const uint8_t mask[9]) {
     unsigned bits = 0;
     for (int i = 0; i < 9; ++i)
       if (mask[i] > 1) fail(GHOM_EINVAL, "mask entries must be 0 or 1");
-    for (int i = 0; i < 9; ++i) {
-      q.mask[i] = mask[i];
-      if (mask[i]) bits |= 1u << i;
-    }
-    c->e->hdesc[0].mask = bits;
+    for (int i = 0; i < 9; ++i) q.user_mask[i] = mask[i];
     q.mask_set = true;
+    apply_control(*c->e, 0);
     return GHOM_OK;
   });
 }
@@ -1404,6 +1423,7 @@ int ghom_set_history(ghom_ctx* c, int nsteps, const double* target) {
     q.target.assign(target, target + 9 * (size_t)nsteps);
     q.nsteps = nsteps;
     q.adapt_fraction = 1.0;
+    apply_control(*c->e, 0);
     return GHOM_OK;
   });
 }
@@ -1484,6 +1504,7 @@ int ghom_step_adaptive(ghom_ctx* c, int max_cuts, int grow_below, ghom_step_info
       tot.newton_iters += q.info.newton_iters;
       tot.cg_iters_total += q.info.cg_iters_total;
       tot.cg_breakdowns += q.info.cg_breakdowns;
+      tot.cg_stalls += q.info.cg_stalls;
       tot.t_cg_ms += q.info.t_cg_ms;
       tot.crit = q.info.crit;
       tot.res_rms = q.info.res_rms;
@@ -1681,8 +1702,9 @@ void visco_history_adjoint(Engine& e, const double* a, double* grad_out) {
       if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg);
       else cg_solve<float>(e, &tcg);
       const CGScalars st = e.host_sc[0];
-      if (st.status == 2 && st.it == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
-      if (st.status == 3) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+      if (st.status == CG_BREAKDOWN && st.it == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
+      if (st.status == CG_CAP) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+      if (st.status == CG_STALLED) fail(GHOM_ENOTCONVERGED, "adjoint CG stalled above its threshold");
       const double* lam = reinterpret_cast<const double*>(e.hdesc[0].x);
       if (e.prec == GHOM_FP32_SPLIT) {
         project64(e, cl, ROLE_REPROJ, "reproj");
@@ -1750,8 +1772,9 @@ int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
     if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg);
     else cg_solve<float>(e, &tcg);
     const CGScalars s = e.host_sc[0];
-    if (s.status == 2 && s.it == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
-    if (s.status == 3) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+    if (s.status == CG_BREAKDOWN && s.it == 0) fail(GHOM_ESINGULAR, "adjoint CG breakdown at its first iteration");
+    if (s.status == CG_CAP) fail(GHOM_ENOTCONVERGED, "adjoint CG reached max_cg");
+    if (s.status == CG_STALLED) fail(GHOM_ENOTCONVERGED, "adjoint CG stalled above its threshold");
     if (e.prec == GHOM_FP32_SPLIT) project64(e, cl, ROLE_REPROJ, "reproj");
     double* grad_dev = nullptr;
     HIPCALL(hipMalloc((void**)&grad_dev, (size_t)N * sizeof(double)));
@@ -1872,6 +1895,13 @@ static int set_option(Engine& e, int key, int value) {
     drop_graphs(e);
     return GHOM_OK;
   }
+  if (key == GHOM_OPT_ROTATION_GAUGE) {
+    if (value != 0 && value != 1) fail(GHOM_EINVAL, "rotation gauge option must be 0 or 1");
+    e.rot_gauge = value != 0;
+    for (size_t p = 0; p < e.P.size(); ++p) apply_control(e, (int)p);
+    upload_descs(e);
+    return GHOM_OK;
+  }
   fail(GHOM_EINVAL, "unknown option");
 }
 
@@ -1883,8 +1913,20 @@ static int get_option(Engine& e, int key, int* value) {
   else if (key == GHOM_OPT_GRAPHS) *value = e.graphs ? 1 : 0;
   else if (key == GHOM_OPT_CHECKPOINTS) *value = e.checkpoints ? 1 : 0;
   else if (key == GHOM_OPT_STREAM_NT) *value = e.stream_nt ? 1 : 0;
+  else if (key == GHOM_OPT_ROTATION_GAUGE) *value = e.rot_gauge ? 1 : 0;
   else fail(GHOM_EINVAL, "unknown option");
   return GHOM_OK;
+}
+
+int ghom_get_control(ghom_ctx* c, uint8_t mask_out[9], int* gauge_axis) {
+  return guard(c, [&]() -> int {
+    const Prob& q = c->e->P[0];
+    if (!q.mask_set) fail(GHOM_ESTATE, "no control mask set");
+    if (mask_out)
+      for (int i = 0; i < 9; ++i) mask_out[i] = q.mask[i];
+    if (gauge_axis) *gauge_axis = q.gauge_axis;
+    return GHOM_OK;
+  });
 }
 
 int ghom_set_option(ghom_ctx* c, int key, int value) {
@@ -1991,15 +2033,11 @@ int ghom_batch_create(ghom_batch** out, const ghom_problem* probs, int nprob, in
       }
       set_material(*e, i, kinds[i], p.phase, p.nphase, tab);
       Prob& q = e->P[i];
-      unsigned bits = 0;
-      for (int c = 0; c < 9; ++c) {
-        q.mask[c] = p.mask[c];
-        if (p.mask[c]) bits |= 1u << c;
-      }
-      e->hdesc[i].mask = bits;
+      for (int c = 0; c < 9; ++c) q.user_mask[c] = p.mask[c];
       q.mask_set = true;
       q.target.assign(p.target, p.target + 9 * (size_t)p.nsteps);
       q.nsteps = p.nsteps;
+      apply_control(*e, i);
     }
     upload_descs(*e);
     return GHOM_OK;

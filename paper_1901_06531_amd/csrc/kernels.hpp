@@ -20,6 +20,7 @@
 
 #include <cstdint>
 
+#include "cg_stop.hpp"
 #include "dft.hpp"
 
 namespace ghom {
@@ -56,10 +57,12 @@ struct CGScalars {
   double alpha;
   double beta;
   double thresh;   // stop when rr <= thresh (= tol^2 N)
+  double best;     // smallest r.r of the solve so far (stall test)
   int it;          // iterations done
   int max_it;
-  int done;        // 1: stop (converged, breakdown or cap)
-  int status;      // 0 running, 1 converged, 2 breakdown, 3 iteration cap
+  int done;        // 1: stop (converged, breakdown, cap or stall)
+  int status;      // CG_RUNNING, CG_CONVERGED, CG_BREAKDOWN, CG_CAP or CG_STALLED (cg_stop.hpp)
+  int since;       // iterations since best was last lowered
 };
 
 constexpr int kRedThreads = 1024;
@@ -1260,12 +1263,14 @@ __device__ __forceinline__ void cg_beta_body(CGScalars* sc, CGScalars* sc_host, 
       sc->beta = s / sc->rr;
       sc->rr = s;
       sc->it += 1;
-      if (s <= sc->thresh) {
+      double best = sc->best;
+      int since = sc->since;
+      const int st = cg_status_after_iteration(s, sc->thresh, sc->it, sc->max_it, best, since);
+      sc->best = best;
+      sc->since = since;
+      if (st != CG_RUNNING) {
         sc->done = 1;
-        sc->status = 1;
-      } else if (sc->it >= sc->max_it) {
-        sc->done = 1;
-        sc->status = 3;
+        sc->status = st;
       }
     }
   }
@@ -1295,7 +1300,7 @@ __device__ __forceinline__ void cg_alpha_block(CGScalars* sc, const double* __re
     sc->pAp = s;
     if (!(s > 0.0) || !isfinite(s)) {
       sc->done = 1;
-      sc->status = 2;
+      sc->status = CG_BREAKDOWN;
     } else {
       sc->alpha = sc->rr / s;
     }
@@ -1609,9 +1614,11 @@ __global__ void cg_start_batch(const ProbDesc* __restrict__ D, const int* __rest
   sc->max_it = d.max_cg;
   sc->it = 0;
   sc->rr = d.rr0;
+  sc->best = d.rr0;
+  sc->since = 0;
   const int stop = !d.active || !(d.rr0 > d.cg_thresh);
   sc->done = stop;
-  sc->status = stop ? 1 : 0;
+  sc->status = stop ? CG_CONVERGED : CG_RUNNING;
   *d.sc_host = *sc;
 }
 

@@ -25,9 +25,11 @@ OPT_ZSLABS = 3
 OPT_GRAPHS = 4
 OPT_CHECKPOINTS = 5
 OPT_STREAM_NT = 6
+OPT_ROTATION_GAUGE = 7
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
           -6: "EDOMAIN", -7: "ESTATE"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 
 
 class GhomError(RuntimeError):
@@ -41,7 +43,8 @@ class StepInfo(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int), ("cg_iters_total", ctypes.c_int),
                 ("cg_breakdowns", ctypes.c_int), ("status", ctypes.c_int),
                 ("crit", ctypes.c_double), ("res_rms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double), ("t_cg_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("t_cg_ms", ctypes.c_double),
+                ("cg_stalls", ctypes.c_int), ("reserved", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,6 +74,7 @@ _SIGS = {
     "ghom_set_time_step": (_i, [_vp, _d]),
     "ghom_set_stiffness_scale": (_i, [_vp, _vp]),
     "ghom_set_control": (_i, [_vp, _vp]),
+    "ghom_get_control": (_i, [_vp, _vp, ctypes.POINTER(_i)]),
     "ghom_set_history": (_i, [_vp, _i, _vp]),
     "ghom_set_tolerances": (_i, [_vp, _d, _d, _d, _i, _i]),
     "ghom_step": (_i, [_vp, ctypes.POINTER(StepInfo)]),
@@ -149,6 +153,20 @@ def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _field_ptr(t, numel, dtype, device, what):
+    """Device pointer of a field tensor after checking what the C ABI cannot: a contiguous
+    tensor of `numel` values of `dtype` on GPU `device`."""
+    if not getattr(t, "is_cuda", False) or not t.is_contiguous():
+        raise ValueError("%s: expected a contiguous device tensor" % what)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, not %s" % (what, dtype, t.dtype))
+    if t.numel() != numel:
+        raise ValueError("%s must hold 9 x N = %d values, not %d" % (what, numel, t.numel()))
+    if t.device.index != device:
+        raise ValueError("%s is on cuda:%s, the solver on cuda:%d" % (what, t.device.index, device))
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _torch_sync():
     import torch
     if torch.cuda.is_available():
@@ -162,6 +180,7 @@ class Solver:
         self.shape = tuple(int(n) for n in shape)
         self.N = int(np.prod(self.shape))
         self.precision = precision
+        self.device = int(device)
         self._c = ctypes.c_void_p()
         rc = lib().ghom_create(ctypes.byref(self._c), *self.shape, *[float(v) for v in lengths],
                                int(precision), int(device), stream)
@@ -232,6 +251,14 @@ class Solver:
         self._check(lib().ghom_set_history(self._c, t.shape[0], _ptr(t)))
         self.nsteps = t.shape[0]
 
+    def control(self):
+        """(mask in use, rotation-gauge axis or -1): the mask as set with the rotation gauge
+        of full stress control applied (ghom_get_control)."""
+        m = np.zeros(9, dtype=np.uint8)
+        a = ctypes.c_int()
+        self._check(lib().ghom_get_control(self._c, _ptr(m), ctypes.byref(a)))
+        return m, a.value
+
     def set_tolerances(self, newton_tol=1e-6, cg_tol=1e-8, cg_forcing=0.0, max_newton=50, max_cg=5000):
         self._check(lib().ghom_set_tolerances(self._c, newton_tol, cg_tol, cg_forcing, max_newton, max_cg))
 
@@ -253,11 +280,17 @@ class Solver:
         return self
 
     # -- solve ---------------------------------------------------------------------------
-    def step(self):
+    def step(self, check=True):
+        """One load increment (ghom_step).  With check=False a failed increment returns its
+        info dict (with 'status' and 'error') instead of raising."""
         info = StepInfo()
         rc = lib().ghom_step(self._c, ctypes.byref(info))
-        self._check(rc)
-        return info.as_dict()
+        if check or rc == 0:
+            self._check(rc)
+            return info.as_dict()
+        d = info.as_dict()
+        d.update(status=rc, error="%s: %s" % (STATUS.get(rc, "?"), lib().ghom_last_error(self._c).decode()))
+        return d
 
     def step_adaptive(self, max_cuts=8, grow_below=2):
         """One load increment in sub-increments (ghom_step_adaptive); the info dict also
@@ -287,6 +320,17 @@ class Solver:
         self._check(lib().ghom_get_field(self._c, int(which), _ptr(out)))
         return out
 
+    def field_device(self, which=FIELD_F, out=None):
+        """Field `which` into a float64 device tensor of shape (9, nx, ny, nz)
+        (ghom_get_field_device)."""
+        import torch
+        if out is None:
+            out = torch.empty((9,) + self.shape, dtype=torch.float64, device=torch.device("cuda", self.device))
+        ptr = _field_ptr(out, 9 * self.N, torch.float64, self.device, "field output")
+        _torch_sync()
+        self._check(lib().ghom_get_field_device(self._c, int(which), ptr))
+        return out
+
     def save_state(self):
         out = np.empty((9,) + self.shape)
         k = ctypes.c_int()
@@ -307,25 +351,27 @@ class Solver:
     def apply_operator(self, v, out=None):
         import torch
         dt = torch.float64 if self.precision == FP64 else torch.float32
-        if v.dtype != dt:
-            raise TypeError("operator input must be %s" % dt)
+        vp = _field_ptr(v, 9 * self.N, dt, self.device, "operator input")
         out = torch.empty_like(v) if out is None else out
+        op = _field_ptr(out, 9 * self.N, dt, self.device, "operator output")
+        if op.value == vp.value:
+            raise ValueError("operator input and output must not overlap")
         _torch_sync()
-        self._check(lib().ghom_apply_operator(self._c, _dev_ptr(v), _dev_ptr(out)))
+        self._check(lib().ghom_apply_operator(self._c, vp, op))
         return out
 
     def apply_projection(self, v, out=None):
         import torch
-        if v.dtype != torch.float64:
-            raise TypeError("projection input must be float64")
+        vp = _field_ptr(v, 9 * self.N, torch.float64, self.device, "projection input")
         out = torch.empty_like(v) if out is None else out
+        op = _field_ptr(out, 9 * self.N, torch.float64, self.device, "projection output")
         _torch_sync()
-        self._check(lib().ghom_apply_projection(self._c, _dev_ptr(v), _dev_ptr(out)))
+        self._check(lib().ghom_apply_projection(self._c, vp, op))
         return out
 
     def residual(self, Pbar):
         import torch
-        out = torch.empty((9,) + self.shape, dtype=torch.float64, device="cuda")
+        out = torch.empty((9,) + self.shape, dtype=torch.float64, device=torch.device("cuda", self.device))
         Pb = np.ascontiguousarray(Pbar, dtype=np.float64).reshape(9)
         _torch_sync()
         self._check(lib().ghom_residual(self._c, _ptr(Pb), _dev_ptr(out)))

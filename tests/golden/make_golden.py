@@ -1,5 +1,5 @@
 """Writes the stored oracle histories under tests/golden/ (run from the repo root:
-``python tests/golden/make_golden.py``).  Only the FP64 oracle computes the values; the
+``python tests/golden/make_golden.py [file ...]``).  Only the FP64 oracle computes the values; the
 inputs come from the seeded generators."""
 
 import json
@@ -31,6 +31,35 @@ def sphere16():
     }
 
 
+def polycrystal32(nsteps=24):
+    """The benchmark's polycrystal generator at 32^3 (512 grains, seeds 2 and 3), full stress
+    control with the P11 triangle wave, increments 1..nsteps (through the first stress-free
+    crossing at increment 20), rotation gauge on, tolerances 1e-10 / 1e-12."""
+    w = synth.workload_polycrystal(n=32)
+    o = go.Oracle(w["shape"])
+    o.set_material_svk(w["phase"], w["C"])
+    o.set_control(w["mask"])
+    o.set_history(w["target"])
+    o.set_tolerances(1e-10, 1e-12)
+    steps = []
+    for k in range(nsteps):
+        r = o.step()
+        print("polycrystal32 increment %d: newton %d cg %d" % (k + 1, r.newton_iters, r.cg_iters), flush=True)
+        steps.append({"F_avg": list(r.F_avg), "P_avg": list(r.P_avg), "newton_iters": r.newton_iters,
+                      "cg_iters": r.cg_iters, "cg_per_newton": r.cg_per_newton})
+    return {
+        "_source": "FP64 oracle (oracle/ghom_oracle.py) on the 32^3 polycrystal (512 rotated-cubic SVK "
+                   "grains) under full stress control with the rotation gauge, P11 triangle wave",
+        "workload": w["name"], "gauge_axis": o.gauge_axis,
+        "newton_tol": 1e-10, "cg_tol": 1e-12, "steps": steps,
+    }
+
+
+WRITERS = {"sphere16_history.json": sphere16, "polycrystal32_history.json": polycrystal32}
+
 if __name__ == "__main__":
-    with open(os.path.join(HERE, "sphere16_history.json"), "w") as f:
-        json.dump(sphere16(), f, indent=1)
+    names = sys.argv[1:] or sorted(WRITERS)
+    for name in names:
+        data = WRITERS[name]()
+        with open(os.path.join(HERE, name), "w") as f:
+            json.dump(data, f, indent=1)

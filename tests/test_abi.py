@@ -55,6 +55,15 @@ def test_new_entry_points_reject_null_contexts():
     assert L.ghom_set_material_visco(None, None, 1, None, None, None) == -1
     assert L.ghom_step_adaptive(None, 4, 2, None, None, None) == -1
     assert L.ghom_set_option(None, 4, 1) == -1
+    assert L.ghom_get_control(None, None, None) == -1
+
+
+def test_binding_checks_device_buffers_before_the_abi():
+    """The C ABI takes no lengths: the binding refuses host tensors, wrong dtypes, wrong
+    sizes and other devices before passing a pointer."""
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError, match="device tensor"):
+        ghom._field_ptr(torch.zeros(9 * 8), 9 * 8, torch.float64, 0, "x")
 
 
 def test_missing_library_fails_loudly(monkeypatch):

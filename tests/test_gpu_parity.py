@@ -2,7 +2,8 @@
 
 FP64 bar: transforms and the operator agree to 1e-12 of the field's largest entry (the
 two sides differ only in rounding order; a 3-D transform pair of n^3 points has a
-round-off of order log2(n^3) * 2^-52 relative); averaged Newton histories to 1e-10.
+round-off of order log2(n^3) * 2^-52 relative); averaged Newton histories to 1e-10
+relative, taken against the norm of <F> and of the largest <P> of the history.
 FP32-split bar: the operator inside CG agrees to 2e-5 of the largest entry (float32
 transforms and tangent); Newton results are stated per test.
 """
@@ -23,7 +24,9 @@ pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 MIXED = synth.mask_uniaxial(0)
 MASKS = {"stress": synth.mask_full_stress(), "strain": synth.mask_full_strain(), "mixed": MIXED}
-SHAPES = [(16, 16, 16), (32, 32, 32), (48, 48, 48), (24, 16, 32), (9, 27, 12), (8, 36, 6), (64, 64, 64)]
+# odd z lengths (12, 16, 9) and (8, 8, 27) exercise the Hermitian completion of odd lines
+SHAPES = [(16, 16, 16), (32, 32, 32), (48, 48, 48), (24, 16, 32), (9, 27, 12), (8, 36, 6), (64, 64, 64),
+          (12, 16, 9), (8, 8, 27)]
 
 
 def say(*a):
@@ -77,7 +80,8 @@ def _svk_tables(n, seed):
     return synth.rotate_C(synth.cubic_C(1.7, 1.2, 0.75), R).reshape(n, 81)
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 32), (48, 48, 48), (9, 27, 12), (64, 64, 64)])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 32), (48, 48, 48), (9, 27, 12), (64, 64, 64),
+                                   (12, 16, 9), (8, 8, 27)])
 @pytest.mark.parametrize("law", ["nh", "svk"])
 @pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
 @pytest.mark.parametrize("xproj", XPROJ)
@@ -136,6 +140,13 @@ def test_residual_and_stress_match_oracle(shape):
     assert rel_err(b, ref) < 1e-12
 
 
+def assert_hist(F, P, F_ref, P_ref, rel, p_scale):
+    """<F> within rel of its norm, <P> within rel of p_scale (the largest norm of <P> over the
+    history: the stress passes through small values)."""
+    assert np.max(np.abs(np.asarray(F) - F_ref)) <= rel * np.linalg.norm(F_ref), (F, F_ref)
+    assert np.max(np.abs(np.asarray(P) - P_ref)) <= rel * p_scale, (P, P_ref)
+
+
 def _run_gpu(w, prec=ghom.FP64, nsteps=None, tols=None, forcing=0.0):
     s = ghom.Solver(w["shape"], precision=prec)
     s.setup(w)
@@ -157,9 +168,9 @@ def test_sphere16_history_matches_oracle():
     gold = json.load(open(os.path.join(GOLD, "sphere16_history.json")))
     s, recs = _run_gpu(synth.workload_sphere16())
     s.close()
+    p_scale = max(np.linalg.norm(st["P_avg"]) for st in gold["steps"])
     for (info, F, P), ref in zip(recs, gold["steps"]):
-        np.testing.assert_allclose(F, ref["F_avg"], rtol=0, atol=1e-10)
-        np.testing.assert_allclose(P, ref["P_avg"], rtol=0, atol=1e-10)
+        assert_hist(F, P, ref["F_avg"], ref["P_avg"], 1e-10, p_scale)
         assert info["newton_iters"] == ref["newton_iters"]
         assert abs(info["cg_iters_total"] - ref["cg_iters"]) <= 2
 
@@ -183,14 +194,19 @@ def test_mixed_particles_history_matches_oracle():
     """Random-sphere neo-Hookean cell (32^3), transverse-stress-free mixed control."""
     say("particles32 mixed fp64")
     w = synth.workload_particles(n=32, seed=1, count=6, nsteps=20)
-    tols = (1e-10, 1e-11)
+    tols = (1e-11, 1e-13)
     o, ref = _oracle_run(w, 2, tols)
     s, recs = _run_gpu(w, nsteps=2, tols=tols)
     Fg = s.field(ghom.FIELD_F)
+    Fd = s.field_device(ghom.FIELD_F).cpu().numpy()
+    Pg = s.field(ghom.FIELD_P)
+    Pd = s.field_device(ghom.FIELD_P).cpu().numpy()
     s.close()
+    # the device copy is the host copy, bit for bit
+    assert np.array_equal(Fd, Fg) and np.array_equal(Pd, Pg)
+    p_scale = max(np.linalg.norm(r.P_avg) for r in ref)
     for (info, F, P), r in zip(recs, ref):
-        np.testing.assert_allclose(F, r.F_avg, rtol=0, atol=1e-10)
-        np.testing.assert_allclose(P, r.P_avg, rtol=0, atol=1e-10)
+        assert_hist(F, P, r.F_avg, r.P_avg, 1e-10, p_scale)
         assert info["newton_iters"] == r.newton_iters
     assert np.max(np.abs(Fg - o.F)) < 1e-9
 
@@ -200,15 +216,17 @@ def test_svk_polycrystal_matches_oracle():
     say("polycrystal16 svk fp64")
     w = synth.workload_polycrystal(n=16, ngrains=12, nsteps=4)
     w["target"] = w["target"] * 5.0
-    tols = (1e-10, 1e-11)
+    tols = (1e-11, 1e-13)
     o, ref = _oracle_run(w, 2, tols)
     s, recs = _run_gpu(w, nsteps=2, tols=tols)
     s.close()
+    p_scale = max(np.linalg.norm(r.P_avg) for r in ref)
     for (info, F, P), r in zip(recs, ref):
-        np.testing.assert_allclose(P, r.P_avg, rtol=0, atol=1e-10)
+        # with the rotation gauge the raw <F> is unique too
+        assert_hist(F, P, r.F_avg, r.P_avg, 1e-10, p_scale)
         C_gpu = F.reshape(3, 3).T @ F.reshape(3, 3)
         C_ref = r.F_avg.reshape(3, 3).T @ r.F_avg.reshape(3, 3)
-        np.testing.assert_allclose(C_gpu, C_ref, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(C_gpu, C_ref, rtol=0, atol=1e-10 * np.linalg.norm(C_ref))
 
 
 def test_fp32_split_sphere16_matches_oracle():
@@ -217,9 +235,9 @@ def test_fp32_split_sphere16_matches_oracle():
     gold = json.load(open(os.path.join(GOLD, "sphere16_history.json")))
     s, recs = _run_gpu(synth.workload_sphere16(), prec=ghom.FP32_SPLIT, forcing=1e-5)
     s.close()
+    p_scale = max(np.linalg.norm(st["P_avg"]) for st in gold["steps"])
     for (info, F, P), ref in zip(recs, gold["steps"]):
-        np.testing.assert_allclose(F, ref["F_avg"], rtol=0, atol=1e-9)
-        np.testing.assert_allclose(P, ref["P_avg"], rtol=0, atol=1e-9)
+        assert_hist(F, P, ref["F_avg"], ref["P_avg"], 1e-9, p_scale)
 
 
 def test_adjoint_matches_oracle():

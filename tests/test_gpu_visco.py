@@ -58,15 +58,16 @@ def _oracle(w):
 def test_visco_history_matches_oracle(control, prec):
     w = _workload((12, 16, 8), control)
     o, ref = _oracle(w)
-    tol = 1e-10 if prec == ghom.FP64 else 1e-8
+    tol = 1e-10 if prec == ghom.FP64 else 1e-9
     with ghom.Solver(w["shape"], precision=prec) as s:
         s.setup(w)
         s.set_tolerances(w["newton_tol"], w["cg_tol"], 1e-5 if prec == ghom.FP32_SPLIT else 0.0)
         for k, rr in enumerate(ref):
             info = s.step()
             F, P = s.averages()
-            say("  %s inc %d: newton %d/%d  P11 %.6e  F11 %.8f" % (control, k + 1, info["newton_iters"],
-                                                                  rr.newton_iters, P[0], F[0]))
+            say("  %s inc %d: newton %d/%d  P11 %.6e  F11 %.8f  dF %.2e dP %.2e" % (
+                control, k + 1, info["newton_iters"], rr.newton_iters, P[0], F[0], np.max(np.abs(F - rr.F_avg)),
+                np.max(np.abs(P - rr.P_avg))))
             if prec == ghom.FP64:
                 assert info["newton_iters"] == rr.newton_iters
             scale = max(1.0, np.max(np.abs(rr.P_avg)))
