@@ -237,6 +237,22 @@ int ghom_apply_operator(ghom_ctx *ctx, const void *v_dev, void *Av_dev);
  * projection of eq. (22) with the context's mask, applied through the 3-D transforms. */
 int ghom_apply_projection(ghom_ctx *ctx, const double *in_dev, double *out_dev);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc): out = G*(in) as ghom_apply_projection computes it, without a context and
+ * without allocating.  The transforms run in a static device array of 24 MiB per GPU, held by
+ * every GPU the library runs on until the process ends, so the grid's half spectrum must fit
+ * in it: at most 64^3 voxels (a larger grid returns GHOM_EINVAL with the sizes).  nx, ny, nz,
+ * Lx, Ly, Lz as in ghom_create; mask (host, 9 bytes) as in ghom_set_control, used as given
+ * (no rotation gauge: there is no history); in_dev and out_dev: float64 device arrays of
+ * 9 x N on GPU `device` (in may equal out).  hip_stream: the stream to run on (NULL: the null
+ * stream).  Returns after the stream has finished.  Every call on one GPU uses the same array
+ * and leaves its contents behind: calls that overlap on one GPU (other threads or streams)
+ * race and must be serialized by the caller.  Errors: GHOM_EINVAL, GHOM_EHIP; the message is
+ * ghom_last_error(NULL). */
+int ghom_apply_projection_static(int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                                 const uint8_t mask[9], const double *in_dev, double *out_dev,
+                                 int device, void *hip_stream);
+
 /* out = -G*(P(F) - P-bar) (float64 device array of 9 x N), the right-hand side of
  * eq. (20) at the current F for the stress target Pbar (host, 9 values; only the
  * stress-controlled components are used).  Also refreshes P and the tangent state. */

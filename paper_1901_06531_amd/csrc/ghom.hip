@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2129,3 +2130,157 @@ int ghom_batch_num_classes(ghom_batch* b) {
 }
 
 }  // extern "C"
+
+// =====================================================================================
+// G* without a context and without device allocation
+// =====================================================================================
+namespace {
+
+// Capacity of the static scratch array on each device: the half spectrum of a 64^3 grid
+// (9 x 64 x 64 x 32 complex doubles, 18 MiB) with the descriptor and twiddle tables.
+constexpr size_t kScratchBytes = (size_t)24 << 20;
+
+}  // namespace
+
+// Device memory of ghom_apply_projection_static, one copy per GPU, held until the process
+// ends.  Host code never passes this name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): it uses the address scratch_address() looked up.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+// This device's address of `scratch`, looked up once per device with the device current.
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    HIPCALL(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw HipFail{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+    g_scratch_dev[device] = ptr;
+  }
+  return g_scratch_dev[device];
+}
+
+// Byte offsets in the scratch for one grid: descriptor, problem id, three twiddle tables,
+// spectrum (9 x nx ny nzh complex doubles).
+struct ScratchLayout {
+  size_t desc, ids, tw[3], spec, total;
+};
+
+ScratchLayout scratch_layout(int nx, int ny, int nz) {
+  ScratchLayout L{};
+  size_t at = 0;
+  L.desc = at;
+  at += align256(sizeof(ProbDesc));
+  L.ids = at;
+  at += align256(sizeof(int));
+  const int ns[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a) {
+    L.tw[a] = at;
+    at += align256((size_t)ns[a] * sizeof(cx<double>));
+  }
+  const size_t nzh = (nz % 2 == 0) ? nz / 2 : (nz + 1) / 2;
+  L.spec = at;
+  at += align256(9 * (size_t)nx * ny * nzh * sizeof(cx<double>));
+  L.total = at;
+  return L;
+}
+
+int static_fail(int code, const std::string& msg) {
+  g_create_err = msg;
+  return code;
+}
+
+}  // namespace
+
+extern "C" int ghom_apply_projection_static(int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                                            const uint8_t mask[9], const double* in_dev, double* out_dev,
+                                            int device, void* hip_stream) {
+  g_create_err.clear();
+  if (!supported_length(nx) || !supported_length(ny) || !supported_length(nz))
+    return static_fail(GHOM_EINVAL, std::string("grid lengths must be among ") + kLengths);
+  if (!(Lx > 0 && Ly > 0 && Lz > 0)) return static_fail(GHOM_EINVAL, "cell lengths must be > 0");
+  if (!mask || !in_dev || !out_dev) return static_fail(GHOM_EINVAL, "null mask or buffer");
+  unsigned bits = 0;
+  for (int c = 0; c < 9; ++c) {
+    if (mask[c] > 1) return static_fail(GHOM_EINVAL, "mask entries must be 0 or 1");
+    if (mask[c]) bits |= 1u << c;
+  }
+  const ScratchLayout L = scratch_layout(nx, ny, nz);
+  if (L.total > kScratchBytes)
+    return static_fail(GHOM_EINVAL, "grid needs " + std::to_string(L.total) + " bytes of scratch; the static scratch holds " +
+                                        std::to_string(kScratchBytes) + " (24 MiB: up to 64^3 voxels)");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev || device >= kMaxScratchDevices)
+    return static_fail(GHOM_EINVAL, "no such device");
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  int rc = GHOM_OK;
+  try {
+    HIPCALL(hipSetDevice(device));
+    char* base = static_cast<char*>(scratch_address(device));
+    // a host-side engine of one problem whose device memory is all in the scratch
+    Engine e;
+    e.device = device;
+    e.stream = static_cast<hipStream_t>(hip_stream);
+    e.prec = GHOM_FP64;
+    e.tsz = 8;
+    e.P.resize(1);
+    ShapeClass c;
+    c.nx = nx;
+    c.ny = ny;
+    c.nz = nz;
+    c.g.nx = nx;
+    c.g.ny = ny;
+    c.g.nz = nz;
+    c.g.nzh = (nz % 2 == 0) ? nz / 2 : (nz + 1) / 2;
+    c.g.N = (long long)nx * ny * nz;
+    c.g.Nh = (long long)nx * ny * c.g.nzh;
+    c.g.invL[0] = 1.0 / Lx;
+    c.g.invL[1] = 1.0 / Ly;
+    c.g.invL[2] = 1.0 / Lz;
+    c.probs = {0};
+    c.ids = reinterpret_cast<int*>(base + L.ids);
+    c.xproj_var[0] = XPROJ_ROWS;
+    ProbDesc hd;
+    std::memset(&hd, 0, sizeof(ProbDesc));
+    hd.g = c.g;
+    hd.mask = bits;
+    hd.active = 1;
+    hd.H = base + L.spec;
+    hd.in = in_dev;
+    hd.out = out_dev;
+    // twiddles W_n^k = exp(-2 pi i k / n), as the contexts build them
+    const int ns[3] = {nx, ny, nz};
+    std::vector<cx<double>> tw[3];
+    for (int a = 0; a < 3; ++a) {
+      tw[a].resize(ns[a]);
+      for (int k = 0; k < ns[a]; ++k) {
+        const CosSin cs = cossin_2pi(k, ns[a]);
+        tw[a][k] = cx<double>{(double)cs.c, (double)-cs.s};
+      }
+      c.tw64[a] = reinterpret_cast<cx<double>*>(base + L.tw[a]);
+      hd.tw64[a] = c.tw64[a];
+      HIPCALL(hipMemcpyAsync(c.tw64[a], tw[a].data(), ns[a] * sizeof(cx<double>), hipMemcpyHostToDevice, e.stream));
+    }
+    const int id0 = 0;
+    HIPCALL(hipMemcpyAsync(c.ids, &id0, sizeof(int), hipMemcpyHostToDevice, e.stream));
+    e.hdesc = &hd;
+    e.ddesc = reinterpret_cast<ProbDesc*>(base + L.desc);
+    upload_descs(e);  // waits for the stream: the host tables above are copied
+    project64(e, c, ROLE_PROJ, "proj");
+    HIPCALL(hipStreamSynchronize(e.stream));
+  } catch (const HipFail& f) {
+    rc = static_fail(GHOM_EHIP, std::string(f.what) + ": " + hipGetErrorString(f.e));
+  } catch (const ApiError& a) {
+    rc = static_fail(a.code, a.msg);
+  } catch (const std::exception& x) {
+    rc = static_fail(GHOM_EHIP, x.what());
+  }
+  if (prev >= 0) (void)hipSetDevice(prev);
+  return rc;
+}

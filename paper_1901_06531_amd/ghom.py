@@ -88,6 +88,7 @@ _SIGS = {
     "ghom_adjoint_grad_scale": (_i, [_vp, _vp, _vp]),
     "ghom_apply_operator": (_i, [_vp, _vp, _vp]),
     "ghom_apply_projection": (_i, [_vp, _vp, _vp]),
+    "ghom_apply_projection_static": (_i, [_i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _i, _vp]),
     "ghom_residual": (_i, [_vp, _vp, _vp]),
     "ghom_batch_create": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _vp]),
     "ghom_batch_destroy": (None, [_vp]),
@@ -171,6 +172,27 @@ def _torch_sync():
     import torch
     if torch.cuda.is_available():
         torch.cuda.synchronize()
+
+
+def apply_projection_static(v, out, mask, lengths=(1.0, 1.0, 1.0), stream=None):
+    """out = G*(v) without a context or any device allocation (ghom_apply_projection_static).
+
+    v and out: float64 device tensors of shape (9, nx, ny, nz) on one GPU (they may be the
+    same tensor), at most 64^3 voxels; mask: 9 entries, 1 = stress-controlled.  The caller
+    provides `out`: nothing is allocated here or in the library."""
+    import torch
+    if v.dim() != 4 or v.shape[0] != 9:
+        raise ValueError("expected a field of shape (9, nx, ny, nz)")
+    nx, ny, nz = (int(n) for n in v.shape[1:])
+    dev = v.device.index if v.device.index is not None else 0
+    vp = _field_ptr(v, 9 * nx * ny * nz, torch.float64, dev, "projection input")
+    op = _field_ptr(out, 9 * nx * ny * nz, torch.float64, dev, "projection output")
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(9)
+    _torch_sync()
+    rc = lib().ghom_apply_projection_static(nx, ny, nz, *[float(L) for L in lengths], _ptr(m), vp, op, dev, stream)
+    if rc != 0:
+        raise GhomError(rc, lib().ghom_last_error(None).decode())
+    return out
 
 
 class Solver:
