@@ -77,6 +77,16 @@ def measured_traffic(kernel, shape):
     return k["read_bytes"] + k["write_bytes"]
 
 
+def steady_launches(samples):
+    """The launches of a kernel record within 10% of its median launch: the steady CG
+    iterations.  Left out (and counted): launches queued after a solve had stopped, which exit
+    at once, and the first iteration of each solve, which moves fewer bytes."""
+    ms = np.asarray(samples, dtype=np.float64)
+    med = float(np.median(ms))
+    keep = ms[(ms >= 0.9 * med) & (ms <= 1.1 * med)]
+    return keep, int(np.sum(ms < 0.2 * med)), int(len(ms) - len(keep) - np.sum(ms < 0.2 * med))
+
+
 def cycled_history(target, total):
     """The periodic load history repeated until it holds `total` increments."""
     reps = -(-total // len(target))
@@ -91,6 +101,7 @@ def run_gpu(w, precision, steps, warmup, profile):
     s.set_history(cycled_history(w["target"], steps + warmup))
     gauge = s.control()[1]
     xproj = {"f64": s.get_option(ghom.OPT_XPROJ_F64), "f32": s.get_option(ghom.OPT_XPROJ_F32)}
+    schedule = s.schedule()
     # both precisions stop CG at max(1e-8, 1e-5 |b|): the float32 CG needs the relative
     # floor, and the float64 run uses the same rule so that the two are compared fairly
     s.set_tolerances(w["newton_tol"], w["cg_tol"], CG_FORCING)
@@ -128,9 +139,13 @@ def run_gpu(w, precision, steps, warmup, profile):
         if one(i + 1, "warmup").get("stuck"):
             raise RuntimeError("warm-up increment %d could not be advanced: %s" % (i + 1, failures[-1]))
     warm_prof = {}
+    warm_steady = {}
     if profile and warmup:
         warm_prof = s.profile()
         op = {k: v for k, v in warm_prof.items() if k.startswith("op_")}
+        for k in op:
+            keep, _, _ = steady_launches(s.profile_samples(k))
+            warm_steady[k] = float(keep.mean())
         s.set_profiling_filter(max(op, key=lambda k: op[k][1]) if op else None)
     import torch
     torch.cuda.synchronize()
@@ -146,11 +161,12 @@ def run_gpu(w, precision, steps, warmup, profile):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = s.profile() if profile else {}
+    samples = {k: s.profile_samples(k) for k in prof} if profile else {}
     F, P = s.averages()
     s.close()
     if warm_prof:
-        log("kernel times (warm-up, every launch timed): " + ", ".join(
-            "%s %.3f ms x%d" % (k, v[1] / v[0], v[0]) for k, v in sorted(warm_prof.items()) if k.startswith("op_")))
+        log("kernel times (warm-up, every launch timed, steady launches): " + ", ".join(
+            "%s %.3f ms" % (k, v) for k, v in sorted(warm_steady.items())))
     cg = sum(i["cg_iters_total"] for i in infos)
     newton = sum(i["newton_iters"] for i in infos)
     N = int(np.prod(w["shape"]))
@@ -171,7 +187,9 @@ def run_gpu(w, precision, steps, warmup, profile):
         "F11": float(F[0]),
         "P11": float(P[0]),
         "xproj_variant": xproj,
-    }, prof
+        "schedule": schedule,
+        "pass_ms_steady": {k: round(v, 4) for k, v in sorted(warm_steady.items())},
+    }, (prof, samples)
 
 
 def run_batch(steps, warmup, sample_per_size=2):
@@ -189,6 +207,9 @@ def run_batch(steps, warmup, sample_per_size=2):
     b = ghom.Batch(ws, precision=ghom.FP32_SPLIT)
     b.set_tolerances(1e-6, 1e-8, CG_FORCING)
     log("batch created in %.1f s (%d launch groups)" % (time.perf_counter() - t0, b.num_classes()))
+    schedules = b.schedules()
+    for sch in schedules:
+        log("  schedule: " + sch)
     for i in range(warmup):
         t0 = time.perf_counter()
         b.step()
@@ -229,16 +250,15 @@ def run_batch(steps, warmup, sample_per_size=2):
                 s_vox += int(np.prod(w["shape"])) * inf["cg_iters_total"]
             torch.cuda.synchronize()
             s_wall += time.perf_counter() - t1
-    return {"problems": len(ws), "launch_groups": 4, "increments_timed": steps,
+    return {"problems": len(ws), "launch_groups": len(schedules), "schedules": schedules, "increments_timed": steps,
             "voxel_iters_per_s": round(vox_its / wall, 1), "ms_per_increment": round(1e3 * wall / steps, 1),
             "one_at_a_time_voxel_iters_per_s": round(s_vox / s_wall, 1),
             "one_at_a_time_sample": "%d problems (%d per grid size), same increments" % (len(sample), sample_per_size)}
 
 
-def cpu_baseline(w, seconds=15.0):
-    """The FP64 oracle timed on this host: CG iterations of the first Newton solve of the
-    given workload (a reduced-size instance of the benchmark's), as voxel-iterations/s,
-    over about `seconds` of CPU work (at least 3 iterations)."""
+def _oracle_cg_rate(w, seconds):
+    """Voxel-iterations/s of the oracle's CG iterations (first Newton solve of increment 1) on
+    workload w, over about `seconds` of CPU work (at least 3 iterations)."""
     from oracle import ghom_oracle as go
 
     o = go.Oracle(w["shape"])
@@ -261,9 +281,47 @@ def cpu_baseline(w, seconds=15.0):
             break
     dt = time.perf_counter() - t0
     N = int(np.prod(w["shape"]))
-    return {"value": N * its / dt, "unit": "voxel-iters/s", "cores": go.WORKERS, "kind": "oracle",
-            "sample": "%d CG iteration(s) of the oracle's first Newton solve on %s, the %d^3 instance of "
-                      "the benchmark's workload generator (%.1f s)" % (its, w["name"], w["shape"][0], dt)}
+    return N * its / dt, its, dt
+
+
+def _oracle_newton_step(w):
+    """Wall time of one oracle Newton iteration at the start of increment 1 (constitutive
+    update, FP64 residual, CG solve at the bench's forcing, update) on workload w, with its CG
+    count."""
+    from oracle import ghom_oracle as go
+
+    o = go.Oracle(w["shape"])
+    o.set_material_svk(w["phase"], w["C"])
+    o.set_control(w["mask"])
+    o.set_history(w["target"])
+    o.set_tolerances(w["newton_tol"], w["cg_tol"], CG_FORCING, 1, 5000)
+    Pbar = np.where(o.mask > 0, w["target"][0], 0.0)
+    t0 = time.perf_counter()
+    b = o.residual(o.stress(), Pbar)
+    dF, its = o.conjugate_gradient(b)
+    o.F = o.F + dF
+    go.Oracle.newton_criterion(dF, o.F.reshape(9, -1).mean(axis=1))
+    return time.perf_counter() - t0, its
+
+
+def cpu_baseline(grid, seconds=15.0):
+    """The FP64 oracle timed on this host (its transforms on every core): CG iterations at
+    the 128^3 and 16^3 instances of the benchmark's generator, and one Newton step at 64^3."""
+    from oracle import ghom_oracle as go
+    from paper_1901_06531_amd import synth
+
+    big = max(16, grid // 2)
+    rate, its, dt = _oracle_cg_rate(synth.workload_polycrystal(n=big), seconds)
+    rate16, its16, dt16 = _oracle_cg_rate(synth.workload_polycrystal(n=16, ngrains=64), 1.0)
+    nt, nits = _oracle_newton_step(synth.workload_polycrystal(n=64))
+    return {"value": rate, "unit": "voxel-iters/s", "cores": go.WORKERS, "kind": "oracle",
+            "sample": "%d CG iteration(s) of the oracle's first Newton solve on the %d^3 instance of the "
+                      "benchmark's polycrystal generator (%.1f s)" % (its, big, dt),
+            "cg_voxel_iters_per_s_16": rate16,
+            "newton_step_s_64": round(nt, 3),
+            "newton_step_sample": "one oracle Newton iteration (constitutive update, FP64 residual, CG solve of "
+                                  "%d iterations at forcing 1e-5, update) at the start of increment 1 on the 64^3 "
+                                  "instance" % nits}
 
 
 def run_paper_example(n, nsteps, precision_name):
@@ -375,7 +433,7 @@ def main():
     log("workload %s built in %.1f s" % (w["name"], time.perf_counter() - t0))
 
     log("FP32-split run")
-    split, prof = run_gpu(w, ghom.FP32_SPLIT, args.steps, args.warmup, profile=True)
+    split, (prof, samples) = run_gpu(w, ghom.FP32_SPLIT, args.steps, args.warmup, profile=True)
     fp64 = None
     if not args.no_fp64:
         log("FP64 run")
@@ -391,12 +449,15 @@ def main():
         launches, ms = op[name]
         wbytes = 4 if name.endswith("f32") else 8
         per_launch = op_bytes(name, N, Nh, wbytes)
-        avg_s = ms / launches / 1e3
-        achieved = per_launch / avg_s / 1e9
+        keep, noop, other = steady_launches(samples[name])
+        avg_ms = float(keep.mean())
+        achieved = per_launch / (avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, w["shape"]),
                 "kernel": name,
-                "avg_ms": round(ms / launches, 4), "bytes_per_launch": per_launch}
+                "avg_ms": round(avg_ms, 4), "bytes_per_launch": per_launch,
+                "launches": {"steady": int(len(keep)), "noop": noop, "other": other,
+                             "all_avg_ms": round(ms / launches, 4)}}
         log("kernel times (timed region): " + ", ".join("%s %.3f ms x%d" % (k, v[1] / v[0], v[0])
                                                         for k, v in sorted(op.items())))
 
@@ -410,7 +471,7 @@ def main():
         log("CPU oracle baseline")
         # the oracle takes about a minute per CG iteration at 256^3: time it on the
         # 128^3 instance of the same generator (same grain count, seeds and loading)
-        cpu = cpu_baseline(synth.workload_polycrystal(n=max(16, args.grid // 2)))
+        cpu = cpu_baseline(args.grid)
 
     out = {
         "metric": METRIC,
@@ -441,6 +502,8 @@ def main():
         "failures": split["failures"],
         "rotation_gauge_axis": split["rotation_gauge_axis"],
         "xproj_variant": split["xproj_variant"],
+        "schedule": split["schedule"],
+        "pass_ms_steady": split["pass_ms_steady"],
         "fp64": None if fp64 is None else {
             "value": round(fp64["voxel_iters_per_s"], 1), "ms_per_step": round(fp64["ms_per_increment"], 3),
             "newton_step_ms": round(fp64["newton_step_ms"], 3), "cg_ms_per_iter": round(fp64["cg_ms_per_iter"], 4),

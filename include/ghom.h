@@ -277,17 +277,37 @@ enum {
                               iteration of all problems together touches more than 256 MB.
                               Passes along transform lines of length >= 128 always stream.
                               Results are the same either way. */
-  GHOM_OPT_ROTATION_GAUGE = 7 /* 1 (default): the rotation gauge of full stress control (see
+  GHOM_OPT_ROTATION_GAUGE = 7, /* 1 (default): the rotation gauge of full stress control (see
                               ghom_set_control); 0: the mask exactly as set.  Takes effect at
                               the next solve. */
+  GHOM_OPT_YPASS_F64 = 8,  /* y-pass (transform along y) variant, float64                   */
+  GHOM_OPT_YPASS_F32 = 9   /* the same for the float32 transforms of GHOM_FP32_SPLIT         */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the fastest variant by timing
  * each on this GPU and grid (done by ghom_create; setting 0 re-times), 1 = "rows" (one
  * thread transforms the three components of a tensor row in turn), 2 = "groups" (three
  * thread groups, one per component, meeting in LDS), 3 = "rows" compiled for at least two
- * wavefronts per SIMD (fewer registers per thread).  All compute the same operator. */
+ * wavefronts per SIMD (fewer registers per thread), 4 = "rows" on the three-stage radix
+ * schedule n = 8 x A1 x 8 (x lengths 128, 256, 512 only: 8 values per thread instead of
+ * the two-stage split's B).  For the y-pass keys: 0 = pick by timing, 1 = "wide" (columns per
+ * workgroup widened to 256-byte segments on lines >= 256), 2 = "narrow" (the plain column
+ * count; only where it differs from "wide"), 3 = three-stage radix schedule (y lengths 128,
+ * 256, 512).  A variant that does not exist for the grid returns GHOM_EINVAL.  All compute the
+ * same operator.
+ *
+ * Tuning at creation is cached for the process, keyed by GPU architecture, pass, precision,
+ * grid, problem count and streaming build, so a second context of the same shape reuses the
+ * choice; with the environment variable GHOM_TUNE_CACHE naming a file, the cache is read from
+ * that file and every new choice is appended to it.  Setting 0 always re-times. */
 int ghom_set_option(ghom_ctx *ctx, int key, int value);
+
+/* The kernel schedule the context runs, as text: grid, and per precision in use the x-pass
+ * and y-pass variants with their radix splits ("16x16": 16 threads per line holding 16
+ * values; "8x4x8": three stages, 32 threads holding 8) and whether the autotuner picked them.
+ * Up to cap bytes (including the terminating zero) go to out (host; nullable).  Returns the
+ * text's length, or GHOM_EINVAL. */
+int ghom_get_schedule(ghom_ctx *ctx, char *out, int cap);
 
 /* GHOM_OPT_ZSLABS: the y-forward, x (projection) and y-inverse passes are run slab by slab
  * over ranges of kz planes, so that a slab's intermediate spectrum can stay in the GPU's
@@ -315,6 +335,13 @@ int ghom_profile_count(ghom_ctx *ctx);
  * the context's stream. */
 int ghom_profile_get(ghom_ctx *ctx, int i, char *name_out, int name_cap, int *launches,
                      double *total_ms);
+
+/* Per-launch times of record i in milliseconds, in launch order: the first min(cap, count)
+ * go to ms_out (host; NULL when cap is 0).  Returns the record's launch count, or a negative
+ * status.  Launches that found nothing to do (CG iterations queued after a solve stopped,
+ * which exit at once) are among them; a caller that wants the time of the launches that did
+ * work separates them by their duration. */
+int ghom_profile_samples(ghom_ctx *ctx, int i, float *ms_out, int cap);
 
 /* Clears the timing records. */
 int ghom_profile_reset(ghom_ctx *ctx);
@@ -376,6 +403,10 @@ int ghom_batch_set_option(ghom_batch *b, int key, int value);
 
 /* Number of launch groups (distinct grid and material law) of the batch. */
 int ghom_batch_num_classes(ghom_batch *b);
+
+/* The kernel schedule of launch group cls (0 <= cls < ghom_batch_num_classes), as
+ * ghom_get_schedule. */
+int ghom_batch_get_schedule(ghom_batch *b, int cls, char *out, int cap);
 
 #ifdef __cplusplus
 }

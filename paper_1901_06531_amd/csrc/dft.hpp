@@ -251,4 +251,30 @@ inline bool supported_length(int n) {
   return with_split(n, [](auto) {});
 }
 
+// ---------------------------------------------------------------------------------
+// three-stage lines: n = B * A1 * A2 with B = A2; A = A1 * A2 threads per line, B values each
+// ---------------------------------------------------------------------------------
+// Stage 1: B-point DFTs in registers over x[q + A b]; stage 2: A2-point DFTs after an LDS
+// exchange (one per thread); stage 3: A1-point DFTs after a second exchange (B / A1 per
+// thread).  Half the values per thread of the two-stage split of the same length, for passes
+// whose registers limit how many waves a SIMD holds.
+template <int B_, int A1_, int A2_> struct Split3 {
+  static constexpr int B = B_, A1 = A1_, A2 = A2_, A = A1_ * A2_, N = B_ * A1_ * A2_;
+  static_assert(A2_ == B_ && B_ % A1_ == 0, "three-stage split: A2 = B and A1 | B");
+};
+
+// Calls f(Split3<...>{}) for a length with a three-stage schedule; returns false otherwise.
+template <typename F> bool with_split3(int n, F&& f) {
+  switch (n) {
+    case 128: f(Split3<8, 2, 8>{}); return true;
+    case 256: f(Split3<8, 4, 8>{}); return true;
+    case 512: f(Split3<8, 8, 8>{}); return true;
+    default: return false;
+  }
+}
+
+inline bool has_split3(int n) {
+  return with_split3(n, [](auto) {});
+}
+
 }  // namespace ghom

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -51,10 +52,12 @@ struct ApiError {
 struct ProfRec {
   int launches = 0;
   double ms = 0.0;
+  std::vector<float> samples;  // each launch's time, in launch order
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
 
-enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2, XPROJ_ROWS_CAPPED = 3 };
+enum { XPROJ_TUNED = 0, XPROJ_ROWS = 1, XPROJ_GROUPS = 2, XPROJ_ROWS_CAPPED = 3, XPROJ_ROWS3 = 4 };
+enum { YPASS_TUNED = 0, YPASS_WIDE = 1, YPASS_NARROW = 2, YPASS_THREE = 3 };
 
 struct ShapeClass {
   int nx = 0, ny = 0, nz = 0, kind = 0;
@@ -64,6 +67,8 @@ struct ShapeClass {
   cx<double>* tw64[3] = {nullptr, nullptr, nullptr};
   cx<float>* tw32[3] = {nullptr, nullptr, nullptr};
   int xproj_var[2] = {XPROJ_TUNED, XPROJ_TUNED};  // [0] float64, [1] float32
+  int ypass_var[2] = {YPASS_TUNED, YPASS_TUNED};  // [0] float64, [1] float32
+  bool tuned_x[2] = {false, false}, tuned_y[2] = {false, false};  // picked by timing (or the tuning cache)
   int vb = 1;                                     // voxel-kernel blocks per problem
 };
 
@@ -196,6 +201,7 @@ void prof_collect(Engine& e) {
       HIPCALL(hipEventElapsedTime(&ms, pr.first, pr.second));
       kv.second.ms += ms;
       kv.second.launches += 1;
+      kv.second.samples.push_back(ms);
       e.ev_pool.push_back(pr.first);
       e.ev_pool.push_back(pr.second);
     }
@@ -270,25 +276,80 @@ int launch_zinv(Engine& e, ShapeClass& c, int role, const std::string& name, int
   return grid;
 }
 
+template <typename T> int& ypass_choice(ShapeClass& c) { return c.ypass_var[sizeof(T) == 8 ? 0 : 1]; }
+
+// whether y-pass variant v exists for line length n (the narrow one only where it differs from
+// the wide one, the three-stage one for lengths with a three-stage schedule)
+template <typename T> bool ypass_has(int v, int n) {
+  if (v == YPASS_WIDE) return true;
+  if (v == YPASS_THREE) return has_split3(n);
+  bool differs = false;
+  with_split(n, [&](auto s) {
+    using S = decltype(s);
+    differs = YCfg<T, S::A, S::B>::TC != YNarrowCfg<T, S::A, S::B>::TC;
+  });
+  return v == YPASS_NARROW && differs;
+}
+
 template <typename T, int DIR>
-void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string& name, int alpha_nparts = 0) {
+void launch_ypass_variant(Engine& e, ShapeClass& c, int v, int role, Slab sl, const std::string& name,
+                          int alpha_nparts) {
+  const long long ncols = 9LL * c.nx * sl.nkz;
+  if (v == YPASS_THREE && with_split3(c.ny, [&](auto s3) {
+        using S3 = decltype(s3);
+        using Cfg = Y3Cfg<T, S3>;
+        const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+        with_nt<S3::N>(e, [&](auto nt) {
+          timed(e, name, [&] {
+            hipLaunchKernelGGL((ypass3_batch<T, S3, DIR, decltype(nt)::value>), dim3(grid, 1, (unsigned)c.probs.size()),
+                               dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl, alpha_nparts);
+          });
+        });
+      }))
+    return;
   with_split(c.ny, [&](auto s) {
     using S = decltype(s);
-    using Cfg = YCfg<T, S::A, S::B>;
-    const long long ncols = 9LL * c.nx * sl.nkz;
-    const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
-    with_nt<S::A * S::B>(e, [&](auto nt) {
-      timed(e, name, [&] {
-        hipLaunchKernelGGL((ypass_batch<T, S::A, S::B, DIR, decltype(nt)::value>),
-                           dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role,
-                           sl, alpha_nparts);
+    auto go = [&](auto wide) {
+      constexpr bool W = decltype(wide)::value;
+      using Cfg = YPassCfg<T, S::A, S::B, W>;
+      const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+      with_nt<S::A * S::B>(e, [&](auto nt) {
+        timed(e, name, [&] {
+          hipLaunchKernelGGL((ypass_batch<T, S::A, S::B, DIR, decltype(nt)::value, W>),
+                             dim3(grid, 1, (unsigned)c.probs.size()), dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role,
+                             sl, alpha_nparts);
+        });
       });
-    });
+    };
+    if constexpr (YCfg<T, S::A, S::B>::TC != YNarrowCfg<T, S::A, S::B>::TC) {
+      if (v == YPASS_NARROW) {
+        go(std::false_type{});
+        return;
+      }
+    }
+    go(std::true_type{});
   });
+}
+
+template <typename T, int DIR>
+void launch_ypass(Engine& e, ShapeClass& c, int role, Slab sl, const std::string& name, int alpha_nparts = 0) {
+  const int v = ypass_choice<T>(c) == YPASS_TUNED ? YPASS_WIDE : ypass_choice<T>(c);
+  launch_ypass_variant<T, DIR>(e, c, v, role, sl, name, alpha_nparts);
 }
 
 template <typename T>
 void launch_xproj_variant(Engine& e, ShapeClass& c, int variant, int role, Slab sl) {
+  if (variant == XPROJ_ROWS3 && with_split3(c.nx, [&](auto s3) {
+        using S3 = decltype(s3);
+        using Cfg = XRows3Cfg<T, S3>;
+        const long long ncols = (long long)c.ny * sl.nkz;
+        const int grid = (int)((ncols + Cfg::TC - 1) / Cfg::TC);
+        with_nt<S3::N>(e, [&](auto nt) {
+          hipLaunchKernelGGL((xproj_rows3_batch<T, S3, decltype(nt)::value>), dim3(grid, 3, (unsigned)c.probs.size()),
+                             dim3(Cfg::NT), 0, e.stream, e.ddesc, c.ids, role, sl);
+        });
+      }))
+    return;
   with_split(c.nx, [&](auto s) {
     using S = decltype(s);
     const long long ncols = (long long)c.ny * sl.nkz;
@@ -334,36 +395,134 @@ void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre, i
   }
 }
 
-// Autotuner: times the x-pass variants on the class's (zeroed, unused) spectra with HIP
-// events and keeps the fastest for this precision and shape.
-template <typename T>
-void tune_xproj(Engine& e, ShapeClass& c) {
+// ---- autotuner --------------------------------------------------------------------------
+// The x pass (transform along x with the projection) and the y passes have several
+// schedules: radix splits (two-stage n = A x B with B values per thread, or three-stage
+// n = B x A1 x A2 with 8 values per thread), register budgets and column counts per
+// workgroup.  At context creation each shape class times the candidates of each pass and
+// precision on its own (zeroed) spectra with HIP events (best of three after a warm-up) and
+// keeps the fastest.  Choices are cached for the process, keyed by GPU architecture, pass,
+// precision, grid, problem count and streaming build; with the environment variable
+// GHOM_TUNE_CACHE naming a file, the cache is read from it at the first tuning and every new
+// choice is appended to it.
+constexpr float kTuneMargin = 0.98f;  // a variant replaces the one kept so far only if 2% faster
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Engine& e, const ShapeClass& c, const char* pass, int prec64) {
+  hipDeviceProp_t prop{};
+  std::string arch = hipGetDeviceProperties(&prop, e.device) == hipSuccess ? std::string(prop.gcnArchName) : "?";
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s:%s:%s:%dx%dx%d:p%zu:nt%d", arch.c_str(), pass, prec64 ? "f64" : "f32", c.nx, c.ny,
+                c.nz, c.probs.size(), e.stream_nt ? 1 : 0);
+  return buf;
+}
+
+bool tune_lookup(const std::string& key, int* v) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (!g_tune_loaded) {
+    g_tune_loaded = true;
+    if (const char* f = std::getenv("GHOM_TUNE_CACHE"))
+      if (FILE* fp = std::fopen(f, "r")) {
+        char k[200];
+        int val = 0;
+        while (std::fscanf(fp, "%199s %d", k, &val) == 2) g_tune_cache[k] = val;
+        std::fclose(fp);
+      }
+  }
+  auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, int v) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[key] = v;
+  if (const char* f = std::getenv("GHOM_TUNE_CACHE"))
+    if (FILE* fp = std::fopen(f, "a")) {
+      std::fprintf(fp, "%s %d\n", key.c_str(), v);
+      std::fclose(fp);
+    }
+}
+
+// best of five timed launches of `launch` after a warm-up (ms)
+template <typename L> float time_best(Engine& e, L&& launch) {
   hipEvent_t e0 = get_event(e), e1 = get_event(e);
-  float best = 0.f;
-  int best_v = XPROJ_ROWS;
-  const Slab full{0, c.g.nzh};
-  for (int v : {XPROJ_ROWS, XPROJ_GROUPS, XPROJ_ROWS_CAPPED}) {
-    launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full);  // warm-up
+  launch();
+  HIPCALL(hipGetLastError());
+  float tmin = 0.f;
+  for (int rep = 0; rep < 5; ++rep) {
+    HIPCALL(hipEventRecord(e0, e.stream));
+    launch();
     HIPCALL(hipGetLastError());
-    float tmin = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
-      HIPCALL(hipEventRecord(e0, e.stream));
-      launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full);
-      HIPCALL(hipGetLastError());
-      HIPCALL(hipEventRecord(e1, e.stream));
-      HIPCALL(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCALL(hipEventElapsedTime(&ms, e0, e1));
-      if (rep == 0 || ms < tmin) tmin = ms;
-    }
-    if (v == XPROJ_ROWS || tmin < best) {
-      best = tmin;
-      best_v = v;
-    }
+    HIPCALL(hipEventRecord(e1, e.stream));
+    HIPCALL(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCALL(hipEventElapsedTime(&ms, e0, e1));
+    if (rep == 0 || ms < tmin) tmin = ms;
   }
   e.ev_pool.push_back(e0);
   e.ev_pool.push_back(e1);
+  return tmin;
+}
+
+template <typename T>
+void tune_xproj(Engine& e, ShapeClass& c, bool use_cache) {
+  const std::string key = tune_key(e, c, "x", sizeof(T) == 8);
+  int v_cached = 0;
+  if (use_cache && tune_lookup(key, &v_cached) && v_cached >= XPROJ_ROWS && v_cached <= XPROJ_ROWS3 &&
+      (v_cached != XPROJ_ROWS3 || has_split3(c.nx))) {
+    xproj_choice<T>(c) = v_cached;
+    c.tuned_x[sizeof(T) == 8 ? 0 : 1] = true;
+    return;
+  }
+  float best = 0.f;
+  int best_v = XPROJ_ROWS;
+  const Slab full{0, c.g.nzh};
+  for (int v : {XPROJ_ROWS, XPROJ_GROUPS, XPROJ_ROWS_CAPPED, XPROJ_ROWS3}) {
+    if (v == XPROJ_ROWS3 && !has_split3(c.nx)) continue;
+    const float t = time_best(e, [&] { launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full); });
+    if (v == XPROJ_ROWS || t < kTuneMargin * best) {  // a challenger must win by the margin
+      best = t;
+      best_v = v;
+    }
+  }
   xproj_choice<T>(c) = best_v;
+  c.tuned_x[sizeof(T) == 8 ? 0 : 1] = true;
+  tune_store(key, best_v);
+}
+
+template <typename T>
+void tune_ypass(Engine& e, ShapeClass& c, bool use_cache) {
+  const std::string key = tune_key(e, c, "y", sizeof(T) == 8);
+  int v_cached = 0;
+  if (use_cache && tune_lookup(key, &v_cached) && v_cached >= YPASS_WIDE && v_cached <= YPASS_THREE &&
+      ypass_has<T>(v_cached, c.ny)) {
+    ypass_choice<T>(c) = v_cached;
+    c.tuned_y[sizeof(T) == 8 ? 0 : 1] = true;
+    return;
+  }
+  float best = 0.f;
+  int best_v = YPASS_WIDE;
+  const Slab full{0, c.g.nzh};
+  for (int v : {YPASS_WIDE, YPASS_NARROW, YPASS_THREE}) {
+    if (!ypass_has<T>(v, c.ny)) continue;
+    const float t = time_best(e, [&] {
+      launch_ypass_variant<T, -1>(e, c, v, ROLE_PROJ, full, "tune", 0);
+      launch_ypass_variant<T, +1>(e, c, v, ROLE_PROJ, full, "tune", 0);
+    });
+    if (v == YPASS_WIDE || t < kTuneMargin * best) {
+      best = t;
+      best_v = v;
+    }
+  }
+  ypass_choice<T>(c) = best_v;
+  c.tuned_y[sizeof(T) == 8 ? 0 : 1] = true;
+  tune_store(key, best_v);
 }
 
 __global__ void fill_zero_kernel(long long n, double* p) {
@@ -371,8 +530,9 @@ __global__ void fill_zero_kernel(long long n, double* p) {
     p[i] = 0.0;
 }
 
-// which: -1 both precisions, 0 float64 only, 1 float32 only
-void tune_class(Engine& e, ShapeClass& c, int which) {
+// which: -1 both precisions, 0 float64 only, 1 float32 only; passes whose choice is
+// XPROJ_TUNED / YPASS_TUNED are timed (or taken from the tuning cache when use_cache)
+void tune_class(Engine& e, ShapeClass& c, int which, bool use_cache = true) {
   for (size_t p = 0; p < e.P.size(); ++p) e.hdesc[p].active = 0;
   for (int p : c.probs) {
     e.hdesc[p].active = 1;
@@ -381,8 +541,14 @@ void tune_class(Engine& e, ShapeClass& c, int which) {
     HIPCALL(hipGetLastError());
   }
   upload_descs(e);
-  if (which != 1) tune_xproj<double>(e, c);
-  if (e.prec == GHOM_FP32_SPLIT && which != 0) tune_xproj<float>(e, c);
+  if (which != 1) {
+    if (xproj_choice<double>(c) == XPROJ_TUNED) tune_xproj<double>(e, c, use_cache);
+    if (ypass_choice<double>(c) == YPASS_TUNED) tune_ypass<double>(e, c, use_cache);
+  }
+  if (e.prec == GHOM_FP32_SPLIT && which != 0) {
+    if (xproj_choice<float>(c) == XPROJ_TUNED) tune_xproj<float>(e, c, use_cache);
+    if (ypass_choice<float>(c) == YPASS_TUNED) tune_ypass<float>(e, c, use_cache);
+  }
   sync(e);
 }
 
@@ -1863,10 +2029,30 @@ static void drop_graphs(Engine& e) {
 
 static int set_option(Engine& e, int key, int value) {
   if (key == GHOM_OPT_XPROJ_F64 || key == GHOM_OPT_XPROJ_F32) {
-    if (value < XPROJ_TUNED || value > XPROJ_ROWS_CAPPED) fail(GHOM_EINVAL, "x-pass variant must be 0, 1, 2 or 3");
+    if (value < XPROJ_TUNED || value > XPROJ_ROWS3) fail(GHOM_EINVAL, "x-pass variant must be 0, 1, 2, 3 or 4");
+    if (value == XPROJ_ROWS3)
+      for (auto& cl : e.C)
+        if (!has_split3(cl.nx)) fail(GHOM_EINVAL, "x-pass variant 4 needs x lengths 128, 256 or 512");
     for (auto& cl : e.C) {
-      cl.xproj_var[key == GHOM_OPT_XPROJ_F64 ? 0 : 1] = value;
-      if (value == XPROJ_TUNED) tune_class(e, cl, key == GHOM_OPT_XPROJ_F64 ? 0 : 1);
+      const int i = key == GHOM_OPT_XPROJ_F64 ? 0 : 1;
+      cl.xproj_var[i] = value;
+      cl.tuned_x[i] = false;
+      if (value == XPROJ_TUNED) tune_class(e, cl, i, false);
+    }
+    drop_graphs(e);
+    return GHOM_OK;
+  }
+  if (key == GHOM_OPT_YPASS_F64 || key == GHOM_OPT_YPASS_F32) {
+    if (value < YPASS_TUNED || value > YPASS_THREE) fail(GHOM_EINVAL, "y-pass variant must be 0, 1, 2 or 3");
+    const bool f64 = key == GHOM_OPT_YPASS_F64;
+    for (auto& cl : e.C)
+      if (value != YPASS_TUNED && !(f64 ? ypass_has<double>(value, cl.ny) : ypass_has<float>(value, cl.ny)))
+        fail(GHOM_EINVAL, "this y-pass variant does not exist for the grid's y length");
+    for (auto& cl : e.C) {
+      const int i = f64 ? 0 : 1;
+      cl.ypass_var[i] = value;
+      cl.tuned_y[i] = false;
+      if (value == YPASS_TUNED) tune_class(e, cl, i, false);
     }
     drop_graphs(e);
     return GHOM_OK;
@@ -1915,8 +2101,55 @@ static int get_option(Engine& e, int key, int* value) {
   else if (key == GHOM_OPT_CHECKPOINTS) *value = e.checkpoints ? 1 : 0;
   else if (key == GHOM_OPT_STREAM_NT) *value = e.stream_nt ? 1 : 0;
   else if (key == GHOM_OPT_ROTATION_GAUGE) *value = e.rot_gauge ? 1 : 0;
+  else if (key == GHOM_OPT_YPASS_F64) *value = e.C[0].ypass_var[0];
+  else if (key == GHOM_OPT_YPASS_F32) *value = e.C[0].ypass_var[1];
   else fail(GHOM_EINVAL, "unknown option");
   return GHOM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// "AxB" of a two-stage split or "BxA1xA2" of a three-stage one
+std::string split_text(int n, bool three) {
+  char buf[32] = "?";
+  if (three) with_split3(n, [&](auto s) { std::snprintf(buf, sizeof buf, "%dx%dx%d", decltype(s)::B, decltype(s)::A1, decltype(s)::A2); });
+  else with_split(n, [&](auto s) { std::snprintf(buf, sizeof buf, "%dx%d", decltype(s)::A, decltype(s)::B); });
+  return buf;
+}
+
+// the schedule class c runs: per precision in use, the x-pass and y-pass variants with their
+// radix splits and whether the autotuner picked them
+std::string schedule_text(const Engine& e, const ShapeClass& c) {
+  static const char* xn[] = {"untuned", "rows", "groups", "rows-capped", "rows3"};
+  static const char* yn[] = {"untuned", "wide", "narrow", "three-stage"};
+  std::string out = std::to_string(c.nx) + "x" + std::to_string(c.ny) + "x" + std::to_string(c.nz) + " (" +
+                    std::to_string(c.probs.size()) + " problem" + (c.probs.size() > 1 ? "s" : "") + ")";
+  for (int i = 0; i < 2; ++i) {
+    if (i == 1 && e.prec != GHOM_FP32_SPLIT) break;
+    const int xv = c.xproj_var[i] == XPROJ_TUNED ? XPROJ_ROWS : c.xproj_var[i];
+    const int yv = c.ypass_var[i] == YPASS_TUNED ? YPASS_WIDE : c.ypass_var[i];
+    out += std::string(i == 0 ? "; f64" : "; f32") + ": x " + xn[xv] + " " + split_text(c.nx, xv == XPROJ_ROWS3) +
+           (c.tuned_x[i] ? " (tuned)" : " (set)") + ", y " + yn[yv] + " " + split_text(c.ny, yv == YPASS_THREE) +
+           (c.tuned_y[i] ? " (tuned)" : " (set)");
+  }
+  return out;
+}
+
+int copy_text(const std::string& t, char* out, int cap) {
+  if (out && cap > 0) {
+    std::strncpy(out, t.c_str(), (size_t)cap - 1);
+    out[cap - 1] = 0;
+  }
+  return (int)t.size();
+}
+}  // namespace
+
+extern "C" {
+
+int ghom_get_schedule(ghom_ctx* c, char* out, int cap) {
+  if (!c || !c->e || cap < 0) return GHOM_EINVAL;
+  return copy_text(schedule_text(*c->e, c->e->C[0]), out, cap);
 }
 
 int ghom_get_control(ghom_ctx* c, uint8_t mask_out[9], int* gauge_axis) {
@@ -1972,6 +2205,24 @@ int ghom_profile_get(ghom_ctx* c, int i, char* name_out, int name_cap, int* laun
     if (total_ms) *total_ms = it->second.ms;
     return GHOM_OK;
   });
+}
+
+int ghom_profile_samples(ghom_ctx* c, int i, float* ms_out, int cap) {
+  if (!c || !c->e) return GHOM_EINVAL;
+  int n = 0;
+  const int rc = guard(c, [&]() -> int {
+    Engine& e = *c->e;
+    if (i < 0 || i >= (int)e.prof_recs.size() || cap < 0 || (cap > 0 && !ms_out))
+      fail(GHOM_EINVAL, "bad record index or output");
+    prof_collect(e);
+    auto it = e.prof_recs.begin();
+    std::advance(it, i);
+    const std::vector<float>& v = it->second.samples;
+    n = (int)v.size();
+    std::copy(v.begin(), v.begin() + std::min(n, cap), ms_out);
+    return GHOM_OK;
+  });
+  return rc == GHOM_OK ? n : rc;
 }
 
 int ghom_profile_reset(ghom_ctx* c) {
@@ -2127,6 +2378,11 @@ int ghom_batch_set_option(ghom_batch* b, int key, int value) {
 int ghom_batch_num_classes(ghom_batch* b) {
   if (!b || !b->e) return GHOM_EINVAL;
   return (int)b->e->C.size();
+}
+
+int ghom_batch_get_schedule(ghom_batch* b, int cls, char* out, int cap) {
+  if (!b || !b->e || cls < 0 || cls >= (int)b->e->C.size() || cap < 0) return GHOM_EINVAL;
+  return copy_text(schedule_text(*b->e, b->e->C[cls]), out, cap);
 }
 
 }  // extern "C"

@@ -19,6 +19,7 @@
 #pragma once
 
 #include <cstdint>
+#include <type_traits>
 
 #include "cg_stop.hpp"
 #include "dft.hpp"
@@ -271,13 +272,125 @@ __device__ __forceinline__ void four_step_second_inv(const cx<T>* v, int q, cons
 }
 
 // ---------------------------------------------------------------------------------
+// three-stage line transforms (Split3): n = B * A1 * A2, A = A1 * A2 threads per line
+// ---------------------------------------------------------------------------------
+// slot(h, l) is this thread's reference to slot h A + l (h < B, l < A) of its line's LDS
+// exchange area; sync() a barrier of every thread sharing that area.
+//
+// Forward (DIR = -1; the inverse with DIR = +1 is three_stage_inv) from v[b] = x[q + A b]:
+//   stage 1: Y[q][c] = W_n^(q c) DFT_B(x[q + A .])[c]                      (registers)
+//   stage 2: thread q takes (c, q1) = (q % B, q / B):
+//            U[c][q1][d1] = W_A^(q1 d1) DFT_A2(Y[q1 + A1 .][c])[d1]
+//   stage 3: task t = q + A i (i < B / A1) takes (c, d1) = (t % B, t / B):
+//            X[c + B (d1 + A2 d2)] = DFT_A1(U[c][.][d1])[d2], kept in v[i A1 + d2]
+// (an A-point DFT over q = q1 + A1 q2, d = d1 + A2 d2, splits as W_A^(q d) =
+// W_A1^(q1 d2) W_A^(q1 d1) W_A2^(q2 d1)).  three_stage_freq gives the frequency of v[e].
+template <typename S>
+__device__ __forceinline__ int three_stage_freq(int q, int e) {
+  const int i = e / S::A1, d2 = e % S::A1;
+  const int t = q + S::A * i;
+  return t % S::B + S::B * (t / S::B + S::A2 * d2);
+}
+
+template <typename S, int DIR, typename T, typename Slot, typename Sync>
+__device__ __forceinline__ void three_stage_fwd(cx<T>* v, int q, const cx<T>* __restrict__ tw, Slot&& slot,
+                                                Sync&& sync) {
+  constexpr int B = S::B, A1 = S::A1, A2 = S::A2, A = S::A;
+  dft<B, DIR>(v);
+#pragma unroll
+  for (int c = 1; c < B; ++c) {
+    const cx<T> w = tw[q * c];
+    v[c] = DIR < 0 ? cmul(v[c], w) : cmulc(v[c], w);
+  }
+  sync();  // earlier readers of the area are done
+#pragma unroll
+  for (int c = 0; c < B; ++c) slot(c, q) = v[c];
+  sync();
+  {
+    const int c = q % B, q1 = q / B;
+    cx<T> t[A2];
+#pragma unroll
+    for (int q2 = 0; q2 < A2; ++q2) t[q2] = slot(c, q1 + A1 * q2);
+    dft<A2, DIR>(t);
+#pragma unroll
+    for (int d1 = 1; d1 < A2; ++d1) {
+      const cx<T> w = tw[B * q1 * d1];  // W_A^(q1 d1) = W_n^(B q1 d1)
+      t[d1] = DIR < 0 ? cmul(t[d1], w) : cmulc(t[d1], w);
+    }
+    sync();
+#pragma unroll
+    for (int d1 = 0; d1 < A2; ++d1) slot(c, d1 * A1 + q1) = t[d1];
+  }
+  sync();
+#pragma unroll
+  for (int i = 0; i < B / A1; ++i) {
+    const int t3 = q + A * i;
+    const int c = t3 % B, d1 = t3 / B;
+    cx<T> u[A1];
+#pragma unroll
+    for (int q1 = 0; q1 < A1; ++q1) u[q1] = slot(c, d1 * A1 + q1);
+    dft<A1, DIR>(u);
+#pragma unroll
+    for (int d2 = 0; d2 < A1; ++d2) v[i * A1 + d2] = u[d2];
+  }
+}
+
+// Inverse of three_stage_fwd (DIR = +1: conjugate twiddles, unnormalized) from the frequency
+// layout of three_stage_fwd back to v[b] = x[q + A b].
+template <typename S, int DIR, typename T, typename Slot, typename Sync>
+__device__ __forceinline__ void three_stage_inv(cx<T>* v, int q, const cx<T>* __restrict__ tw, Slot&& slot,
+                                                Sync&& sync) {
+  constexpr int B = S::B, A1 = S::A1, A2 = S::A2, A = S::A;
+  sync();  // earlier readers of the area are done
+#pragma unroll
+  for (int i = 0; i < B / A1; ++i) {
+    const int t3 = q + A * i;
+    const int c = t3 % B, d1 = t3 / B;
+    cx<T> u[A1];
+#pragma unroll
+    for (int d2 = 0; d2 < A1; ++d2) u[d2] = v[i * A1 + d2];
+    dft<A1, DIR>(u);
+#pragma unroll
+    for (int q1 = 0; q1 < A1; ++q1) slot(c, d1 * A1 + q1) = u[q1];
+  }
+  sync();
+  {
+    const int c = q % B, q1 = q / B;
+    cx<T> t[A2];
+#pragma unroll
+    for (int d1 = 0; d1 < A2; ++d1) {
+      const cx<T> z = slot(c, d1 * A1 + q1);
+      const cx<T> w = tw[B * q1 * d1];
+      t[d1] = DIR < 0 ? cmul(z, w) : cmulc(z, w);
+    }
+    dft<A2, DIR>(t);
+    sync();
+#pragma unroll
+    for (int q2 = 0; q2 < A2; ++q2) slot(c, q1 + A1 * q2) = t[q2];
+  }
+  sync();
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    const cx<T> w = tw[q * c];
+    const cx<T> z = slot(c, q);
+    v[c] = DIR < 0 ? cmul(z, w) : cmulc(z, w);
+  }
+  dft<B, DIR>(v);
+}
+
+// ---------------------------------------------------------------------------------
 // y pass: in-place complex transform along y of every spectrum line (c, x, kz)
 // ---------------------------------------------------------------------------------
-template <typename T, int A, int B, int DIR, bool NTS>
+// the y pass's column configuration: WIDE the widened one (YCfg), else the plain one
+template <typename T, int A, int B> using YNarrowCfg = ColCfg<T, A, B, 64, 256>;
+template <typename T, int A, int B, bool WIDE> using YPassCfg =
+    typename std::conditional<WIDE, YCfg<T, A, B>, YNarrowCfg<T, A, B>>::type;
+
+template <typename T, int A, int B, int DIR, bool NTS, bool WIDE = true>
 __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw,
                                            const CGScalars* __restrict__ sc, int bx) {
   constexpr bool kNT = NTS;  // nontemporal streamed accesses
-  using Cfg = YCfg<T, A, B>;
+  using Cfg = YPassCfg<T, A, B, WIDE>;
   constexpr int TC = Cfg::TC;
   constexpr int RS = Cfg::RS;
   __shared__ cx<T> lds[Cfg::LDS];
@@ -301,6 +414,54 @@ __device__ __forceinline__ void ypass_body(const Geo& g, Slab sl, cx<T>* __restr
   if (ok) {
 #pragma unroll
     for (int e = 0; e < B; ++e) st_cx<kNT>(&H[base + (long long)(q + A * e) * rs], v[e]);
+  }
+}
+
+// y pass with the three-stage schedule (Split3): A threads per line holding B values, TC
+// lines per workgroup, LDS of n slots per line with one padding row per A slots.  The forward
+// pass writes X[k] where the three-stage layout leaves it; the inverse reads it from there.
+template <typename T, typename S> struct Y3Cfg {
+  static constexpr int TC = S::A >= 64 ? 8 : 16;  // at most 512 threads per workgroup
+  static constexpr int NT = S::A * TC;
+  static constexpr int LDS = (S::N + S::N / S::A) * TC;
+};
+
+template <typename T, typename S, int DIR, bool NTS>
+__device__ __forceinline__ void ypass3_body(const Geo& g, Slab sl, cx<T>* __restrict__ H, const cx<T>* __restrict__ tw,
+                                            const CGScalars* __restrict__ sc, int bx) {
+  constexpr bool kNT = NTS;
+  using Cfg = Y3Cfg<T, S>;
+  constexpr int TC = Cfg::TC, A = S::A, B = S::B;
+  __shared__ cx<T> lds[Cfg::LDS];
+  if (sc && sc->done) return;
+  const int j = threadIdx.x % TC;
+  const int q = threadIdx.x / TC;
+  const long long ncols = 9LL * g.nx * sl.nkz;
+  const long long col = (long long)bx * TC + j;
+  const bool ok = col < ncols;
+  const long long grp = col / sl.nkz;  // (c, x)
+  const long long base = grp * ((long long)g.ny * g.nzh) + sl.kz0 + (col - grp * sl.nkz);
+  const long long rs = g.nzh;
+  auto slot = [&](int h, int l) -> cx<T>& { return lds[(h * (A + 1) + l) * TC + j]; };
+  auto sync = [] { __syncthreads(); };
+  cx<T> v[B];
+  if constexpr (DIR < 0) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = ok ? ld_cx<kNT>(&H[base + (long long)(q + A * b) * rs]) : cx<T>{0, 0};
+    three_stage_fwd<S, -1>(v, q, tw, slot, sync);
+    if (ok) {
+#pragma unroll
+      for (int e = 0; e < B; ++e) st_cx<kNT>(&H[base + (long long)three_stage_freq<S>(q, e) * rs], v[e]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < B; ++e)
+      v[e] = ok ? ld_cx<kNT>(&H[base + (long long)three_stage_freq<S>(q, e) * rs]) : cx<T>{0, 0};
+    three_stage_inv<S, +1>(v, q, tw, slot, sync);
+    if (ok) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) st_cx<kNT>(&H[base + (long long)(q + A * b) * rs], v[b]);
+    }
   }
 }
 
@@ -517,6 +678,87 @@ __device__ __forceinline__ void xproj_rows_body(const Geo& g, Slab sl, cx<T>* __
       cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + gcol;
 #pragma unroll
       for (int e = 0; e < B; ++e) st_cx<kNT>(&dst[(long long)(q + A * e) * rs], v[e]);
+    }
+  }
+}
+
+// x pass with the three-stage schedule ("rows3"): as "rows", one thread takes the three
+// components of a tensor row in turn, but a line has A = 32 (n = 256) threads holding 8
+// values each, so a thread's registers hold 8 values and 8 projection accumulators instead
+// of 16 + 16.  TC columns (ky, kz) per workgroup; LDS exchange area of n slots per column
+// with one padding row per A slots.
+template <typename T, typename S> struct XRows3Cfg {
+  static constexpr int TC = S::A >= 64 ? 8 : 16;  // at most 512 threads per workgroup
+  static constexpr int NT = S::A * TC;
+  static constexpr int SLOTS = S::N + S::N / S::A;
+  static constexpr int LDS = SLOTS * TC;
+};
+
+template <typename T, typename S, bool NTS>
+__device__ __forceinline__ void xproj_rows3_body(const Geo& g, Slab sl, cx<T>* __restrict__ H,
+                                                 const cx<T>* __restrict__ tw, const ProjParams& pp,
+                                                 const CGScalars* __restrict__ sc, int bx, int by) {
+  constexpr bool kNT = NTS;
+  using Cfg = XRows3Cfg<T, S>;
+  constexpr int TC = Cfg::TC, A = S::A, B = S::B;
+  __shared__ cx<T> lds[Cfg::LDS];
+  __shared__ cx<T> a0s[3];
+  if (sc && sc->done) return;
+  const int j = threadIdx.x % TC;
+  const int q = threadIdx.x / TC;
+  const int row = by;
+  const long long ncols = (long long)g.ny * sl.nkz;
+  const long long col = (long long)bx * TC + j;
+  const bool ok = col < ncols;
+  const long long rs = (long long)g.ny * g.nzh;
+  const int ky = ok ? (int)(col / sl.nkz) : 0;
+  const int kz = ok ? sl.kz0 + (int)(col - (long long)ky * sl.nkz) : 0;
+  const long long gcol = (long long)ky * g.nzh + kz;
+  const bool nyq_yz = ((g.ny % 2 == 0) && ky == g.ny / 2);
+  const T xy = (T)(signed_k(ky, g.ny) * g.invL[1]);
+  const T xz = (T)(kz * g.invL[2]);
+  const T post = (T)pp.post;
+  const bool hold0 = ok && ky == 0 && kz == 0 && q == 0;  // v[0] of thread 0 holds kx = 0
+  auto slot = [&](int h, int l) -> cx<T>& { return lds[(h * (A + 1) + l) * TC + j]; };
+  auto sync = [] { __syncthreads(); };
+  auto xi_x = [&](int e) { return (T)(signed_k(three_stage_freq<S>(q, e), g.nx) * g.invL[0]); };
+  cx<T> s[B];
+#pragma unroll
+  for (int e = 0; e < B; ++e) s[e] = cx<T>{0, 0};
+#pragma nounroll
+  for (int l = 0; l < 3; ++l) {
+    const cx<T>* src = H + (long long)(3 * row + l) * g.Nh + gcol;
+    cx<T> v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = ok ? ld_cx<kNT>(&src[(long long)(q + A * b) * rs]) : cx<T>{0, 0};
+    three_stage_fwd<S, -1>(v, q, tw, slot, sync);
+#pragma unroll
+    for (int e = 0; e < B; ++e) s[e] = s[e] + v[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
+    if (hold0) a0s[l] = v[0];
+  }
+#pragma unroll
+  for (int e = 0; e < B; ++e) {
+    const int kx = three_stage_freq<S>(q, e);
+    const bool nyq = nyq_yz || ((g.nx % 2 == 0) && kx == g.nx / 2);
+    const T xx = xi_x(e);
+    const T xi2 = xx * xx + xy * xy + xz * xz;
+    s[e] = (nyq || xi2 == (T)0) ? cx<T>{0, 0} : s[e] * (post / xi2);
+  }
+#pragma nounroll
+  for (int l = 0; l < 3; ++l) {
+    cx<T> v[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) v[e] = s[e] * (l == 0 ? xi_x(e) : (l == 1 ? xy : xz));
+    if (hold0) {  // xi = 0: eq. (22) keeps stress-controlled components (minus P-bar)
+      const int c = 3 * row + l;
+      const cx<T> a0 = a0s[l];
+      v[0] = ((pp.mask >> c) & 1u) ? cx<T>{(a0.re - (T)pp.off(c)) * post, a0.im * post} : cx<T>{0, 0};
+    }
+    three_stage_inv<S, +1>(v, q, tw, slot, sync);
+    if (ok) {
+      cx<T>* dst = H + (long long)(3 * row + l) * g.Nh + gcol;
+#pragma unroll
+      for (int b = 0; b < B; ++b) st_cx<kNT>(&dst[(long long)(q + A * b) * rs], v[b]);
     }
   }
 }
@@ -1487,17 +1729,30 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
 
 // alpha_nparts > 0: block 0 of each problem first sets the CG step's alpha from that many
 // partials of the forward z pass
-template <typename T, int A, int B, int DIR, bool NTS>
-__global__ void __launch_bounds__((YCfg<T, A, B>::NT))
+template <typename T, int A, int B, int DIR, bool NTS, bool WIDE = true>
+__global__ void __launch_bounds__((YPassCfg<T, A, B, WIDE>::NT))
 ypass_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl, int alpha_nparts) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
   if (alpha_nparts > 0 && blockIdx.x == 0) {
-    cg_alpha_block<YCfg<T, A, B>::NT>(d.sc, d.partials, alpha_nparts);
+    cg_alpha_block<YPassCfg<T, A, B, WIDE>::NT>(d.sc, d.partials, alpha_nparts);
     __syncthreads();  // a breakdown (done = 1) is seen by every thread of the block below
   }
-  ypass_body<T, A, B, DIR, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
-                           blockIdx.x);
+  ypass_body<T, A, B, DIR, NTS, WIDE>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1),
+                                      role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x);
+}
+
+template <typename T, typename S, int DIR, bool NTS>
+__global__ void __launch_bounds__((Y3Cfg<T, S>::NT))
+ypass3_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl, int alpha_nparts) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  if (alpha_nparts > 0 && blockIdx.x == 0) {
+    cg_alpha_block<Y3Cfg<T, S>::NT>(d.sc, d.partials, alpha_nparts);
+    __syncthreads();
+  }
+  ypass3_body<T, S, DIR, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 1), role == ROLE_OP_CG ? d.sc : nullptr,
+                              blockIdx.x);
 }
 
 // WAVES > 1: at least that many waves per SIMD, a register cap (the "rows, capped" variant;
@@ -1527,6 +1782,16 @@ xproj_groups_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, 
   const ProjParams pp = proj_params(d, role);
   xproj_groups_body<T, A, B, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
                              role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, typename S, bool NTS>
+__global__ void __launch_bounds__((XRows3Cfg<T, S>::NT))
+xproj_rows3_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role, Slab sl) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const ProjParams pp = proj_params(d, role);
+  xproj_rows3_body<T, S, NTS>(d.g, sl, reinterpret_cast<cx<T>*>(d.H), twd<T>(d, 0), pp,
+                              role == ROLE_OP_CG ? d.sc : nullptr, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, int A, int B, typename TOUT, int ZM, bool NTS>

@@ -26,6 +26,8 @@ OPT_GRAPHS = 4
 OPT_CHECKPOINTS = 5
 OPT_STREAM_NT = 6
 OPT_ROTATION_GAUGE = 7
+OPT_YPASS_F64 = 8
+OPT_YPASS_F32 = 9
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
           -6: "EDOMAIN", -7: "ESTATE"}
@@ -101,10 +103,13 @@ _SIGS = {
     "ghom_batch_num_classes": (_i, [_vp]),
     "ghom_set_option": (_i, [_vp, _i, _i]),
     "ghom_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
+    "ghom_get_schedule": (_i, [_vp, ctypes.c_char_p, _i]),
+    "ghom_batch_get_schedule": (_i, [_vp, _i, ctypes.c_char_p, _i]),
     "ghom_set_profiling": (_i, [_vp, _i]),
     "ghom_set_profiling_filter": (_i, [_vp, ctypes.c_char_p]),
     "ghom_profile_count": (_i, [_vp]),
     "ghom_profile_get": (_i, [_vp, _i, ctypes.c_char_p, _i, ctypes.POINTER(_i), _dp]),
+    "ghom_profile_samples": (_i, [_vp, _i, _vp, _i]),
     "ghom_profile_reset": (_i, [_vp]),
 }
 
@@ -408,6 +413,14 @@ class Solver:
         self._check(lib().ghom_get_option(self._c, int(key), ctypes.byref(v)))
         return v.value
 
+    def schedule(self):
+        """The kernel schedule in use (ghom_get_schedule)."""
+        buf = ctypes.create_string_buffer(512)
+        n = lib().ghom_get_schedule(self._c, buf, 512)
+        if n < 0:
+            self._check(n)
+        return buf.value.decode()
+
     # -- profiling -----------------------------------------------------------------------
     def set_profiling(self, on=True):
         self._check(lib().ghom_set_profiling(self._c, int(bool(on))))
@@ -426,6 +439,23 @@ class Solver:
             self._check(lib().ghom_profile_get(self._c, i, buf, 128, ctypes.byref(cnt), ctypes.byref(ms)))
             out[buf.value.decode()] = (cnt.value, ms.value)
         return out
+
+    def profile_samples(self, name):
+        """Per-launch milliseconds of the record `name` (ghom_profile_samples)."""
+        n = lib().ghom_profile_count(self._c)
+        buf = ctypes.create_string_buffer(128)
+        for i in range(n):
+            self._check(lib().ghom_profile_get(self._c, i, buf, 128, None, None))
+            if buf.value.decode() == name:
+                cnt = lib().ghom_profile_samples(self._c, i, None, 0)
+                if cnt < 0:
+                    self._check(cnt)
+                out = np.zeros(cnt, dtype=np.float32)
+                got = lib().ghom_profile_samples(self._c, i, _ptr(out), cnt)
+                if got < 0:
+                    self._check(got)
+                return out
+        raise KeyError(name)
 
     def profile_reset(self):
         self._check(lib().ghom_profile_reset(self._c))
@@ -503,6 +533,17 @@ class Batch:
 
     def num_classes(self):
         return lib().ghom_batch_num_classes(self._b)
+
+    def schedules(self):
+        """The kernel schedule of every launch group (ghom_batch_get_schedule)."""
+        out = []
+        buf = ctypes.create_string_buffer(512)
+        for i in range(self.num_classes()):
+            n = lib().ghom_batch_get_schedule(self._b, i, buf, 512)
+            if n < 0:
+                self._check(n)
+            out.append(buf.value.decode())
+        return out
 
     def step(self, raise_on_error=True):
         infos = (StepInfo * self.n)()

@@ -7,6 +7,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -56,3 +57,20 @@ def test_json_line_has_the_contract_fields():
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
     assert roof["traffic"] is None  # counters were taken on the 256^3 workload
+
+
+def test_steady_launch_filter():
+    """The roofline's launch average keeps the launches within 10% of the median (the steady
+    CG iterations) and counts the no-op launches and the others apart."""
+    ms = [0.008] * 3 + [0.50] * 2 + [0.586, 0.585, 0.587, 0.588, 0.584, 0.583, 0.59] * 3
+    keep, noop, other = bench.steady_launches(ms)
+    assert noop == 3 and other == 2 and len(keep) == 21
+    assert abs(keep.mean() - np.mean([0.586, 0.585, 0.587, 0.588, 0.584, 0.583, 0.59])) < 1e-12
+
+
+def test_cpu_baseline_samples_run_on_tiny_instances():
+    from paper_1901_06531_amd import synth
+    rate, its, dt = bench._oracle_cg_rate(synth.workload_polycrystal(n=8, ngrains=8), 0.01)
+    assert rate > 0 and its >= 3
+    t, nits = bench._oracle_newton_step(synth.workload_polycrystal(n=8, ngrains=8))
+    assert t > 0 and nits >= 1

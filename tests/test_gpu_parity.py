@@ -48,6 +48,51 @@ def random_F(shape, g, amp=0.1):
 
 
 XPROJ = [1, 2, 3]  # the x-pass variants ("rows", "groups", "rows" with a register cap)
+# lengths with a three-stage radix schedule along x and y (128 = 8x2x8, 512 = 8x8x8)
+SHAPES3 = [(128, 8, 12), (16, 128, 9), (512, 4, 4), (4, 512, 6)]
+
+
+@pytest.mark.parametrize("shape", SHAPES3)
+@pytest.mark.parametrize("mask", ["stress", "mixed"])
+def test_three_stage_schedules_match_oracle(shape, mask):
+    """Projection and operator with every x-pass and y-pass variant the grid has, the
+    three-stage ones included, against the oracle."""
+    say("three-stage schedules", shape, mask)
+    g = np.random.default_rng(4)
+    A = g.standard_normal((9,) + shape)
+    ref = go.apply_projection(A, MASKS[mask])
+    F = random_F(shape, g)
+    phase = g.integers(0, 8, size=shape).astype(np.uint16)
+    C = _svk_tables(8, 4)
+    o = go.Oracle(shape)
+    o.set_material_svk(phase, C)
+    o.set_control(MASKS[mask])
+    v = g.standard_normal((9,) + shape)
+    ref_op = o.apply_operator(v, F)
+    for prec in (ghom.FP64, ghom.FP32_SPLIT):
+        kx = ghom.OPT_XPROJ_F64 if prec == ghom.FP64 else ghom.OPT_XPROJ_F32
+        ky = ghom.OPT_YPASS_F64 if prec == ghom.FP64 else ghom.OPT_YPASS_F32
+        dt = torch.float64 if prec == ghom.FP64 else torch.float32
+        with ghom.Solver(shape, precision=prec) as s:
+            s.set_material_svk(phase, C)
+            s.set_control(MASKS[mask])
+            s.load_state(F, 0)
+            seen = 0
+            for xv in (1, 2, 3, 4):
+                for yv in (1, 2, 3):
+                    try:
+                        s.set_option(kx, xv)
+                        s.set_option(ky, yv)
+                    except ghom.GhomError:
+                        continue  # the variant does not exist for this grid
+                    seen += 1
+                    if prec == ghom.FP64:
+                        out = s.apply_projection(dev(A)).cpu().numpy()
+                        assert rel_err(out, ref) < 1e-12, (xv, yv)
+                    got = s.apply_operator(dev(v, dt)).double().cpu().numpy()
+                    assert rel_err(got, ref_op) < (1e-12 if prec == ghom.FP64 else 2e-5), (prec, xv, yv)
+            # the three-stage variant of the long axis was among them
+            assert seen >= 4 + (shape[1] in (128, 512))
 
 
 @pytest.mark.parametrize("shape", SHAPES)
