@@ -42,10 +42,10 @@ def op_bytes(name, N, Nh, w, svk=True, update_p=True):
         return 2 * spec
     if "zfwd" in name:
         state = (9 if svk else 12) * N * w + (2 * N if svk else 0)  # SVK: H = F - I (no scale plane), phase
-        # CG step: r, p in, p out (p = r + beta p folded in)
-        return field * (3 if update_p else 1) + state + spec
-    if "zinv" in name:  # CG step: spectrum, x, r, p in; x, r out
-        return spec + 5 * field
+        # CG step: r, p, x in; x, p out (x += alpha p of the previous step, p = r + beta p)
+        return field * (5 if update_p else 1) + state + spec
+    if "zinv" in name:  # CG step: spectrum, r in; r out (r -= alpha Ap)
+        return spec + 2 * field
     return None
 
 

@@ -401,7 +401,8 @@ void middle_passes(Engine& e, ShapeClass& c, int role, const std::string& pre, i
 // n = B x A1 x A2 with 8 values per thread), register budgets and column counts per
 // workgroup.  At context creation each shape class times the candidates of each pass and
 // precision on its own (zeroed) spectra with HIP events (best of three after a warm-up) and
-// keeps the fastest.  Choices are cached for the process, keyed by GPU architecture, pass,
+// keeps the fastest, timing each candidate inside the y-forward, x, y-inverse sequence the
+// pipeline runs.  Choices are cached for the process, keyed by GPU architecture, pass,
 // precision, grid, problem count and streaming build; with the environment variable
 // GHOM_TUNE_CACHE naming a file, the cache is read from it at the first tuning and every new
 // choice is appended to it.
@@ -483,9 +484,15 @@ void tune_xproj(Engine& e, ShapeClass& c, bool use_cache) {
   float best = 0.f;
   int best_v = XPROJ_ROWS;
   const Slab full{0, c.g.nzh};
+  // timed in context: the y passes around it as the pipeline runs them
+  const int yv = ypass_choice<T>(c) == YPASS_TUNED ? YPASS_WIDE : ypass_choice<T>(c);
   for (int v : {XPROJ_ROWS, XPROJ_GROUPS, XPROJ_ROWS_CAPPED, XPROJ_ROWS3}) {
     if (v == XPROJ_ROWS3 && !has_split3(c.nx)) continue;
-    const float t = time_best(e, [&] { launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full); });
+    const float t = time_best(e, [&] {
+      launch_ypass_variant<T, -1>(e, c, yv, ROLE_PROJ, full, "tune", 0);
+      launch_xproj_variant<T>(e, c, v, ROLE_PROJ, full);
+      launch_ypass_variant<T, +1>(e, c, yv, ROLE_PROJ, full, "tune", 0);
+    });
     if (v == XPROJ_ROWS || t < kTuneMargin * best) {  // a challenger must win by the margin
       best = t;
       best_v = v;
@@ -509,10 +516,12 @@ void tune_ypass(Engine& e, ShapeClass& c, bool use_cache) {
   float best = 0.f;
   int best_v = YPASS_WIDE;
   const Slab full{0, c.g.nzh};
+  const int xv = xproj_choice<T>(c) == XPROJ_TUNED ? XPROJ_ROWS : xproj_choice<T>(c);
   for (int v : {YPASS_WIDE, YPASS_NARROW, YPASS_THREE}) {
     if (!ypass_has<T>(v, c.ny)) continue;
     const float t = time_best(e, [&] {
       launch_ypass_variant<T, -1>(e, c, v, ROLE_PROJ, full, "tune", 0);
+      launch_xproj_variant<T>(e, c, xv, ROLE_PROJ, full);
       launch_ypass_variant<T, +1>(e, c, v, ROLE_PROJ, full, "tune", 0);
     });
     if (v == YPASS_WIDE || t < kTuneMargin * best) {
@@ -693,8 +702,10 @@ void constitutive_residual(Engine& e) {
 
 // Conjugate gradients on A dF = b from dF = 0 for every active problem; the stop test of
 // each problem is set in its descriptor (cg_thresh, max_cg).  Returns when all are done.
+// finish: apply the step of the last completed iteration to x here (the Newton update, which
+// reads x anyway, applies it itself and passes false)
 template <typename T>
-void cg_solve(Engine& e, double* t_ms) {
+void cg_solve(Engine& e, double* t_ms, bool finish = true) {
   const auto t0 = std::chrono::steady_clock::now();
   long long vox = 0;
   for (auto& c : e.C) {
@@ -772,17 +783,24 @@ void cg_solve(Engine& e, double* t_ms) {
   }
   // the chunk queued last returns at once; wait for it, so that the scalars are final
   HIPCALL(hipEventSynchronize(e.sc_ev[1 - slot]));
-  // the first iteration writes x; a problem that stopped before it gets x = 0
-  bool zeroed = false;
+  // a problem that stopped before its first step gets x = 0
   for (auto& c : e.C)
     for (int p : c.probs)
       if (e.hdesc[p].active && e.host_sc[p].it == 0 && e.host_sc[p].status == CG_CONVERGED) {
         const long long nd = (9LL * c.g.N * (long long)sizeof(T) + 7) / 8;  // arena buffers are padded
         hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, e.stream, nd, reinterpret_cast<double*>(e.hdesc[p].x));
         HIPCALL(hipGetLastError());
-        zeroed = true;
       }
-  if (zeroed) sync(e);
+  // the step the last completed iteration took reaches the iterate here (the forward pass of
+  // the iteration after it would have applied it)
+  for (auto& c : e.C) {
+    if (!finish || !class_active(e, c)) continue;
+    timed(e, "cg_finish", [&] {
+      hipLaunchKernelGGL(cg_finish_batch<T>, dim3(c.vb, 1, (unsigned)c.probs.size()), dim3(kVoxThreads), 0, e.stream,
+                         e.ddesc, c.ids);
+    });
+  }
+  sync(e);
   if (t_ms) *t_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -882,8 +900,8 @@ void newton(Engine& e, const std::vector<int>& set) {
     set_active_from_running(e, set);
     if (!any_running(e, set)) break;
     double tcg = 0.0;
-    if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg);
-    else cg_solve<float>(e, &tcg);
+    if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg, false);  // newton_update applies the pending step
+    else cg_solve<float>(e, &tcg, false);
     for (int p : set) {
       Prob& q = e.P[p];
       if (!q.running) continue;

@@ -66,6 +66,16 @@ struct CGScalars {
   int since;       // iterations since best was last lowered
 };
 
+// After a CG solve: whether the step of the last completed iteration still has to reach the
+// iterate (the forward pass of the iteration after it applies it, and none ran after a stop by
+// convergence, cap or stall): 0 no (x is complete; x = 0 when the solve stopped before its
+// first step), 1 x = alpha p (a single step: x was never written), 2 x = x + alpha p.
+__device__ __forceinline__ int cg_pending_mode(const CGScalars* sc) {
+  const int st = sc->status;
+  if (sc->it < 1 || (st != CG_CONVERGED && st != CG_CAP && st != CG_STALLED)) return 0;
+  return sc->it >= 2 ? 2 : 1;
+}
+
 constexpr int kRedThreads = 1024;
 constexpr int kRedFlag = 31;  // slot of the det F <= 0 flag in a problem's 32 reduced values
 
@@ -998,10 +1008,16 @@ template <int MODE> constexpr int zfwd_ntmin() {
 template <typename T, typename TIN>
 struct ZfwdArgs {
   const TIN* in;              // Z_PLAIN: field to transform (9 planes)
+  const TIN* pend;            // Z_PLAIN, Newton re-projection: the CG direction whose pending step
+  TIN pend_alpha;             //   pend_alpha pend is added to `in` (pend_mode 2) or replaces it (1)
+  int pend_mode;
   T* p;                       // Z_NH/Z_SVK: CG direction (updated in place when update_p)
   T* r;                       // CG residual
+  T* x;                       // CG iterate: update_p == 1 applies the previous step's alpha p to it
+  int x_mode;                 // update_p == 1: 1 x <- alpha p (x not yet written), 2 x <- x + alpha p
+  T alpha;                    // the previous CG step's alpha
   const double* b;            // update_p == 2: the Newton right-hand side
-  int update_p;               // 0: p as is; 1: p <- r + beta p; 2 (CG start): r <- b, p <- b
+  int update_p;               // 0: p as is; 1: x <- x + alpha p, p <- r + beta p; 2 (CG start): r <- b, p <- b
   const T* state;             // tangent state planes
   const uint16_t* phase;      // SVK: phase of each voxel
   const T* C6;                // SVK: per-phase 6x6 Voigt stiffness in the CG type
@@ -1068,14 +1084,24 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 #pragma unroll
         for (int c = 0; c < 9; ++c) dv[k][c] = (T)ld_s<kNT>(&args.b[c * N + vx[k]]);
     } else if (args.update_p == 1) {
-      T rv[SD][9];
+      // the CG iterate takes the previous step's alpha p here, where p is read anyway (so the
+      // inverse pass reads neither x nor p); p <- r + beta p
+      T rv[SD][9], xv[SD][9];
+      const bool xadd = args.x_mode == 2;
 #pragma unroll
       for (int k = 0; k < SD; ++k)
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           rv[k][c] = ld_s<kNT>(&args.r[c * N + vx[k]]);
           dv[k][c] = ld_s<kNT>(&args.p[c * N + vx[k]]);
+          xv[k][c] = xadd ? ld_s<kNT>(&args.x[c * N + vx[k]]) : (T)0;
         }
+#pragma unroll
+      for (int k = 0; k < SD; ++k) {
+        if (!ok[k]) continue;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) st_s<kNT>(&args.x[c * N + vx[k]], xv[k][c] + args.alpha * dv[k][c]);
+      }
 #pragma unroll
       for (int k = 0; k < SD; ++k)
 #pragma unroll
@@ -1155,6 +1181,7 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
   for (int k = 0; k < (CONST ? 18 : 1); ++k) cs[k] = 0.0;
   int bad = 0;
   const T beta = (CG && args.update_p == 1) ? (T)args.sc->beta : (T)0;
+
   // phase 1: per-voxel values into LDS, line pair (2m, 2m+1) -> (re, im)
   if constexpr (CG) {
     constexpr int SD = zpf_depth<T, true>((2 * LP * NZ + NT - 1) / NT);
@@ -1167,8 +1194,16 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
     if (line < nlines) {
       const long long vox = line * NZ + z;
       if constexpr (MODE == Z_PLAIN) {
+        if (args.pend_mode) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) val[c] = (T)ld_s<kNT>(&args.in[c * g.N + vox]);
+          for (int c = 0; c < 9; ++c) {
+            const TIN xin = args.pend_mode == 2 ? ld_s<kNT>(&args.in[c * g.N + vox]) : (TIN)0;
+            val[c] = (T)(xin + args.pend_alpha * ld_s<kNT>(&args.pend[c * g.N + vox]));
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) val[c] = (T)ld_s<kNT>(&args.in[c * g.N + vox]);
+        }
       } else {  // fused residual: constitutive update
         double f[9], pv[9];
 #pragma unroll
@@ -1254,10 +1289,7 @@ template <typename T, typename TOUT>
 struct ZinvArgs {
   const cx<T>* H;
   TOUT* out;                  // ZI_PLAIN: 9 planes
-  TOUT* x;                    // ZI_CG
-  TOUT* r;
-  const TOUT* p;
-  int first;                  // ZI_CG: first iteration (x is not read)
+  TOUT* r;                    // ZI_CG: r <- r - alpha Ap (the iterate is updated by the next forward pass)
   double* F;                  // ZI_NEWTON
   int self_dot;               // ZI_PLAIN: partial sum of out . out per block
   double* partials;           // ZI_CG / self_dot: one per block; ZI_NEWTON: 10 columns
@@ -1352,20 +1384,14 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
     }
     if constexpr (ZM == ZI_CG) {
       constexpr int SD = zpf_depth<TOUT, false>(IT);
-      const bool first = args.first;
 #pragma unroll
       for (int c0 = 0; c0 < IT; c0 += SD) {
-        TOUT xv[SD][9], pv[SD][9], rv[SD][9];
+        TOUT rv[SD][9];
 #pragma unroll
         for (int k = 0; k < SD; ++k) {
           const long long v = c0 + k < IT ? vx[c0 + k] : 0;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            const long long i = c * N + v;
-            xv[k][c] = first ? (TOUT)0 : ld_s<kNT>(&args.x[i]);
-            pv[k][c] = ld_s<kNT>(&args.p[i]);
-            rv[k][c] = ld_s<kNT>(&args.r[i]);
-          }
+          for (int c = 0; c < 9; ++c) rv[k][c] = ld_s<kNT>(&args.r[c * N + v]);
         }
 #pragma unroll
         for (int k = 0; k < SD; ++k) {
@@ -1378,11 +1404,8 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
-            const long long i = c * N + vx[it];
-            const TOUT xn = xv[k][c] + alpha * pv[k][c];
             const TOUT rn = rv[k][c] - alpha * o;
-            st_s<kNT>(&args.x[i], xn);
-            st_s<kNT>(&args.r[i], rn);
+            st_s<kNT>(&args.r[c * N + vx[it]], rn);
             acc += (double)rn * (double)rn;
           }
         }
@@ -1569,9 +1592,11 @@ __device__ __forceinline__ void sum_columns_body(const double* __restrict__ part
   }
 }
 
-// F += dF; partials: max |dF(x)|^2 and sums of F (10 columns)
+// F += dF; partials: max |dF(x)|^2 and sums of F (10 columns).  dF is the CG iterate x with
+// the solve's pending step (cg_pending_mode) added here: dF = [x] + alpha p.
 template <typename TD>
-__device__ __forceinline__ void newton_update_body(const Geo& g, double* __restrict__ F, const TD* __restrict__ dF,
+__device__ __forceinline__ void newton_update_body(const Geo& g, double* __restrict__ F, const TD* __restrict__ x,
+                                                   const TD* __restrict__ p, TD alpha, int mode,
                                                    double* __restrict__ partials, int bx, int gx) {
   __shared__ double red[10 * (kVoxThreads / 64)];
   double mx = 0.0;
@@ -1582,8 +1607,9 @@ __device__ __forceinline__ void newton_update_body(const Geo& g, double* __restr
     double n2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      const double d = (double)dF[c * g.N + v];
-      const double fn = F[c * g.N + v] + d;
+      const long long i = c * g.N + v;
+      const double d = mode == 0 ? (double)x[i] : (double)((mode == 2 ? x[i] : (TD)0) + alpha * p[i]);
+      const double fn = F[i] + d;
       F[c * g.N + v] = fn;
       n2 += d * d;
       sums[c] += fn;
@@ -1708,10 +1734,16 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
     a.in = role == ROLE_RESID ? reinterpret_cast<const TIN*>(d.P)
                               : ((role == ROLE_REPROJ || role == ROLE_NEWTON) ? reinterpret_cast<const TIN*>(d.x)
                                                      : reinterpret_cast<const TIN*>(d.in));
+    if (role == ROLE_NEWTON) {  // the Newton correction: the CG iterate with the solve's pending step
+      a.pend = reinterpret_cast<const TIN*>(d.p);
+      a.pend_alpha = (TIN)d.sc->alpha;
+      a.pend_mode = cg_pending_mode(d.sc);
+    }
   } else {
     const bool cg = role == ROLE_OP_CG;
     a.p = cg ? reinterpret_cast<T*>(d.p) : const_cast<T*>(reinterpret_cast<const T*>(d.in));
     a.r = reinterpret_cast<T*>(d.r);
+    a.x = cg ? reinterpret_cast<T*>(d.x) : nullptr;
     a.b = d.b;
     a.update_p = cg ? update_p : 0;
     a.state = reinterpret_cast<const T*>(d.state);
@@ -1721,6 +1753,10 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
     a.has_scale = d.has_scale;
     a.partials = cg ? d.partials : nullptr;
     a.sc = cg ? d.sc : nullptr;
+    if (cg && update_p == 1) {  // sc->it steps are done: the pending iterate update is step it - 1's
+      a.x_mode = d.sc->it == 1 ? 1 : 2;
+      a.alpha = (T)d.sc->alpha;
+    }
   }
   a.H = reinterpret_cast<cx<T>*>(d.H);
   a.tw = twd<T>(d, 2);
@@ -1804,11 +1840,8 @@ zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
   a.tw = twd<T>(d, 2);
   a.partials = d.partials;
   if constexpr (ZM == ZI_CG) {
-    a.x = reinterpret_cast<TOUT*>(d.x);
     a.r = reinterpret_cast<TOUT*>(d.r);
-    a.p = reinterpret_cast<const TOUT*>(d.p);
     a.sc = d.sc;
-    a.first = first;
   } else if constexpr (ZM == ZI_NEWTON) {
     a.F = d.F;
     a.pstride = (int)gridDim.x;
@@ -1895,6 +1928,25 @@ cg_beta_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int n
   cg_beta_body(d.sc, d.sc_host, d.partials, nparts);
 }
 
+// End of a CG solve: the step the last iteration completed (converged, cap or stall, with
+// at least one step) has not yet moved the iterate, since the forward pass of the following
+// iteration applies it: x <- x + alpha p (x <- alpha p after a single step).  After a
+// breakdown the forward pass of the breaking iteration has applied it already.
+template <typename T>
+__global__ void __launch_bounds__(kVoxThreads)
+cg_finish_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
+  const ProbDesc& d = D[ids[blockIdx.z]];
+  if (!d.active) return;
+  const int mode = cg_pending_mode(d.sc);
+  if (!mode) return;
+  const T alpha = (T)d.sc->alpha;
+  T* x = reinterpret_cast<T*>(d.x);
+  const T* p = reinterpret_cast<const T*>(d.p);
+  const long long n = 9 * d.g.N;
+  for (long long i = (long long)blockIdx.x * kVoxThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVoxThreads)
+    x[i] = (mode == 2 ? x[i] : (T)0) + alpha * p[i];
+}
+
 // layout 0: entry (i, k) at i * K + k; layout 1: at k * nparts + i.  Results go to
 // red[off .. off + K).
 __global__ void __launch_bounds__(kRedThreads)
@@ -1913,7 +1965,8 @@ __global__ void __launch_bounds__(kVoxThreads)
 newton_update_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
   const ProbDesc& d = D[ids[blockIdx.z]];
   if (!d.active) return;
-  newton_update_body<double>(d.g, d.F, reinterpret_cast<const double*>(d.x), d.partials, blockIdx.x, gridDim.x);
+  newton_update_body<double>(d.g, d.F, reinterpret_cast<const double*>(d.x), reinterpret_cast<const double*>(d.p),
+                             d.sc->alpha, cg_pending_mode(d.sc), d.partials, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kVoxThreads)

@@ -340,3 +340,44 @@ def test_failure_modes_are_reported():
         with pytest.raises(ghom.GhomError) as e:
             s.step()
         assert e.value.name == "ESTATE"
+
+
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_single_step_cg_solves_match_oracle(prec):
+    """Homogeneous neo-Hookean cell with only P11 prescribed (every other component of F held
+    at the identity): each Newton system is one-dimensional, so every CG solve ends after one
+    step and its iterate is that step alone (the pending-step path where x was never written).
+    The history, the 0-D closed form and the adjoint (one-step solve again) match the oracle."""
+    say("single-step CG solves", prec)
+    shape = (8, 8, 8)
+    mask = np.zeros(9, np.uint8)
+    mask[0] = 1
+    target = np.tile(np.eye(3).reshape(9), (3, 1))
+    target[:, 0] = [0.02, 0.04, 0.06]  # P11 on the stress-controlled component
+    phase = np.zeros(shape, np.uint16)
+    o = go.Oracle(shape)
+    o.set_material_neohookean(phase, [1.0], [2.0])
+    o.set_control(mask)
+    o.set_history(target)
+    o.set_tolerances(1e-12, 1e-13)
+    ref = go.run_history(o)
+    assert all(c == 1 for r in ref for c in r.cg_per_newton if c)
+    with ghom.Solver(shape, precision=prec) as s:
+        s.set_material_neohookean(phase, [1.0], [2.0])
+        s.set_control(mask)
+        s.set_history(target)
+        s.set_tolerances(1e-12, 1e-13, 0.0 if prec == ghom.FP64 else 1e-5)
+        for k, r in enumerate(ref):
+            info = s.step()
+            F, P = s.averages()
+            assert info["cg_iters_total"] <= info["newton_iters"]  # at most one step per solve
+            tol = 1e-12 if prec == ghom.FP64 else 1e-9
+            assert abs(F[0] - r.F_avg[0]) < tol and abs(P[0] - target[k, 0]) < tol
+            # 0-D: mu (a - 1/a) + lam ln(a) / a = p with the other entries of F at the identity
+            a = F[0]
+            assert abs(1.0 * (a - 1 / a) + 2.0 * np.log(a) / a - target[k, 0]) < 10 * tol
+        a9 = np.zeros(9)
+        a9[0] = 1.0
+        g_gpu = s.adjoint_grad_scale(a9)
+    g_ref = o.adjoint_grad_scale(a9)
+    assert rel_err(g_gpu, g_ref) < (1e-10 if prec == ghom.FP64 else 1e-5)
