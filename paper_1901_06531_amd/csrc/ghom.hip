@@ -561,6 +561,15 @@ void tune_class(Engine& e, ShapeClass& c, int which, bool use_cache = true) {
   sync(e);
 }
 
+// Column sums (first nmax columns: maxima) of every problem's partials table into red[off ..
+// off + K): one block per problem and column.
+void launch_sum_columns(Engine& e, const int* ids, int np, int nparts, int K, int nmax, int layout, int off,
+                        int with_flag) {
+  hipLaunchKernelGGL(sum_columns_batch, dim3(np, K), dim3(kRedThreads), 0, e.stream, e.ddesc, ids, nparts, K, nmax,
+                     layout, off, with_flag);
+  HIPCALL(hipGetLastError());
+}
+
 // out = scale * G*(in - Pbar) in float64 for every active problem of a class
 // role: ROLE_RESID (P -> b, with b.b partials), ROLE_REPROJ (x -> dF64), ROLE_PROJ (in -> out),
 // ROLE_NEWTON (F += G*(x), Newton-update partials)
@@ -621,8 +630,7 @@ void constitutive(Engine& e) {
       }
     });
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 18, 0, 0,
-                         0, 1);
+      launch_sum_columns(e, c.ids, np, c.vb, 18, 0, 0, 0, 1);
     });
   }
   const size_t n = e.P.size();
@@ -667,14 +675,12 @@ void constitutive_residual(Engine& e) {
       else gz = launch_zfwd<double, Z_CONST_VISCO, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
     }
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gz, 18, 0, 1, 0,
-                         1);
+      launch_sum_columns(e, c.ids, np, gz, 18, 0, 1, 0, 1);
     });
     middle_passes<double>(e, c, ROLE_RESID, "res_");
     const int gi = launch_zinv<double, double, ZI_PLAIN>(e, c, ROLE_RESID, "res_zinv_f64");
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 1, 0, 0,
-                         kRedB, 0);
+      launch_sum_columns(e, c.ids, np, gi, 1, 0, 0, kRedB, 0);
     });
   }
   const size_t n = e.P.size();
@@ -813,8 +819,7 @@ void newton_update(Engine& e, std::vector<double>& crit) {
     if (e.prec == GHOM_FP32_SPLIT) {
       const int gi = project64(e, c, ROLE_NEWTON, "reproj");
       timed(e, "reduce", [&] {
-        hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, gi, 10, 1, 1,
-                           0, 0);
+        launch_sum_columns(e, c.ids, np, gi, 10, 1, 1, 0, 0);
       });
       continue;
     }
@@ -822,8 +827,7 @@ void newton_update(Engine& e, std::vector<double>& crit) {
       hipLaunchKernelGGL(newton_update_batch, dim3(c.vb, 1, np), dim3(kVoxThreads), 0, e.stream, e.ddesc, c.ids);
     });
     timed(e, "reduce", [&] {
-      hipLaunchKernelGGL(sum_columns_batch, dim3(np), dim3(kRedThreads), 0, e.stream, e.ddesc, c.ids, c.vb, 10, 1, 0,
-                         0, 0);
+      launch_sum_columns(e, c.ids, np, c.vb, 10, 1, 0, 0, 0);
     });
   }
   const size_t n = e.P.size();
@@ -1874,7 +1878,7 @@ void visco_history_adjoint(Engine& e, const double* a, double* grad_out) {
       e.hdesc[0].active = 1;
       upload_descs(e);
       const int gi = project64(e, cl, ROLE_ADJ, "adj");
-      hipLaunchKernelGGL(sum_columns_batch, dim3(1), dim3(kRedThreads), 0, e.stream, e.ddesc, cl.ids, gi, 1, 0, 0, 20, 0);
+      launch_sum_columns(e, cl.ids, 1, gi, 1, 0, 0, 20, 0);
       HIPCALL(hipGetLastError());
       sync(e);
       const double rr = e.host_red[20];

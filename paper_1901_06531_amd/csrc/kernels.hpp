@@ -1504,16 +1504,16 @@ __device__ __forceinline__ void constitutive_body(const Geo& g, const double* __
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ base, int nparts, long long stride,
                                                   double* red) {
   constexpr int NT = kRedThreads;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = 0.0;
   int i = threadIdx.x;
-  for (; i + 3 * NT < nparts; i += 4 * NT) {
-    a0 += base[(long long)i * stride];
-    a1 += base[(long long)(i + NT) * stride];
-    a2 += base[(long long)(i + 2 * NT) * stride];
-    a3 += base[(long long)(i + 3 * NT) * stride];
+  for (; i + 7 * NT < nparts; i += 8 * NT) {  // eight loads in flight per thread
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += base[(long long)(i + k * NT) * stride];
   }
-  for (; i < nparts; i += NT) a0 += base[(long long)i * stride];
-  return block_sum<NT>((a0 + a1) + (a2 + a3), red);
+  for (; i < nparts; i += NT) a[0] += base[(long long)i * stride];
+  return block_sum<NT>(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])), red);
 }
 
 // beta = r'.r' / r.r from the inverse z pass's partials, the iteration count and the stop
@@ -1572,24 +1572,26 @@ __device__ __forceinline__ void cg_alpha_block(CGScalars* sc, const double* __re
   }
 }
 
-// column sums of a partials table (entry (i, k) at partials[i * si + k * sk], i < nparts,
-// k < K) into out[0..K); the first nmax columns are reduced with max instead of sum (one
-// block, fixed order)
-__device__ __forceinline__ void sum_columns_body(const double* __restrict__ partials, int nparts, int K, int nmax,
-                                                 long long si, long long sk, double* __restrict__ out) {
+// column k of a partials table (entry (i, k) at partials[i * si + k * sk], i < nparts) into
+// out[k], reduced with max instead of sum if use_max (one block per column, fixed order)
+__device__ __forceinline__ void sum_column_body(const double* __restrict__ partials, int nparts, int k, bool use_max,
+                                                long long si, long long sk, double* __restrict__ out) {
   __shared__ double red[kRedThreads / 64];
-  for (int k = 0; k < K; ++k) {
-    double r;
-    const double* base = partials + (long long)k * sk;
-    if (k < nmax) {
-      double acc = 0.0;
-      for (int i = threadIdx.x; i < nparts; i += kRedThreads) acc = fmax(acc, base[(long long)i * si]);
-      r = block_max<kRedThreads>(acc, red);
-    } else {
-      r = reduce_partials(base, nparts, si, red);
+  const double* base = partials + (long long)k * sk;
+  double r;
+  if (use_max) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 3 * kRedThreads < nparts; i += 4 * kRedThreads) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = fmax(acc[u], base[(long long)(i + u * kRedThreads) * si]);
     }
-    if (threadIdx.x == 0) out[k] = r;
+    for (; i < nparts; i += kRedThreads) acc[0] = fmax(acc[0], base[(long long)i * si]);
+    r = block_max<kRedThreads>(fmax(fmax(acc[0], acc[1]), fmax(acc[2], acc[3])), red);
+  } else {
+    r = reduce_partials(base, nparts, si, red);
   }
+  if (threadIdx.x == 0) out[k] = r;
 }
 
 // F += dF; partials: max |dF(x)|^2 and sums of F (10 columns).  dF is the CG iterate x with
@@ -1948,15 +1950,17 @@ cg_finish_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids) {
 }
 
 // layout 0: entry (i, k) at i * K + k; layout 1: at k * nparts + i.  Results go to
-// red[off .. off + K).
+// red[off .. off + K); the first nmax columns are maxima.  Grid: (problems, K), one block per
+// column of a problem.
 __global__ void __launch_bounds__(kRedThreads)
 sum_columns_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int nparts, int K, int nmax,
                   int layout, int off, int with_flag) {
   const ProbDesc& d = D[ids[blockIdx.x]];
   if (!d.active) return;
-  sum_columns_body(d.partials, nparts, K, nmax, layout ? 1 : K, layout ? nparts : 1, d.red + off);
+  const int k = blockIdx.y;
+  sum_column_body(d.partials, nparts, k, k < nmax, layout ? 1 : K, layout ? nparts : 1, d.red + off);
   // the det F <= 0 flag of the constitutive update (set by device atomics) rides along
-  if (with_flag && threadIdx.x == 0) d.red[kRedFlag] = (double)*d.flag;
+  if (with_flag && k == 0 && threadIdx.x == 0) d.red[kRedFlag] = (double)*d.flag;
 }
 
 // F += x in FP64 mode (in FP32-split mode the re-projection's inverse pass applies the
