@@ -199,7 +199,10 @@ int ghom_get_averages(ghom_ctx *ctx, double Fbar[9], double Pbar[9]);
 
 /* Copies field `which` (GHOM_FIELD_F or GHOM_FIELD_P, float64, 9 x N, layout above) to host
  * memory: the microscopic deformation gradient F(x) and stress P(F(x)) of Sec. 2.1 at the
- * current state (the unknown of eq. 3-5 and its stress).  GHOM_EINVAL for another `which`. */
+ * current state (the unknown of eq. 3-5 and its stress).  GHOM_EINVAL for another `which`.
+ * For the elastic laws the Newton iteration does not store P(x) (it needs only its transform
+ * and average); the first request after an evaluation computes it from F(x) by one pass over
+ * the field, which leaves the averages as they were. */
 int ghom_get_field(ghom_ctx *ctx, int which, double *host_out);
 
 /* Same into caller-owned device memory (float64, 9 x N): waits for the context's stream,

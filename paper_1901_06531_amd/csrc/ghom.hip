@@ -86,6 +86,8 @@ struct Prob {
   double Favg[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double Pavg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   bool state_valid = false;
+  // the P field matches F (the residual pass of the elastic laws does not store it)
+  bool p_field_valid = false;
   double adapt_fraction = 1.0;  // adaptive stepping: fraction the next increment starts with
   // solve bookkeeping
   bool running = false;
@@ -600,9 +602,9 @@ int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
 }
 
 // ------------------------------------------------------------------ method steps -------
-// Constitutive update of every active problem: P, tangent state, <F>, <P>.  Problems with
-// det F <= 0 get EDOMAIN and stop.
-void constitutive(Engine& e) {
+// Constitutive update of every active problem: P, tangent state, <F>, <P> (the averages are
+// left as they are if !averages).  Problems with det F <= 0 get EDOMAIN and stop.
+void constitutive(Engine& e, bool averages = true) {
   for (auto& c : e.C) {
     if (!class_active(e, c)) continue;
     const int np = (int)c.probs.size();
@@ -639,11 +641,14 @@ void constitutive(Engine& e) {
     if (!e.hdesc[p].active) continue;
     Prob& q = e.P[p];
     const double N = (double)e.C[q.cls].g.N;
-    for (int i = 0; i < 9; ++i) {
-      q.Favg[i] = e.host_red[32 * p + i] / N;
-      q.Pavg[i] = e.host_red[32 * p + 9 + i] / N;
+    if (averages) {
+      for (int i = 0; i < 9; ++i) {
+        q.Favg[i] = e.host_red[32 * p + i] / N;
+        q.Pavg[i] = e.host_red[32 * p + 9 + i] / N;
+      }
     }
     q.state_valid = true;
+    q.p_field_valid = true;
     if (e.host_red[32 * p + kRedFlag] != 0.0) {
       q.state_valid = false;
       q.status = GHOM_EDOMAIN;
@@ -655,7 +660,9 @@ void constitutive(Engine& e) {
 
 // One Newton evaluation for every active problem: the constitutive update (P, tangent
 // state, <F>, <P>; det F <= 0 gives EDOMAIN) fused into the forward pass of the FP64
-// residual b = -G*(P - Pbar); sets rms_b and the r.r the next CG solve starts from.
+// residual b = -G*(P - Pbar); sets rms_b and the r.r the next CG solve starts from.  The P
+// field itself is stored for the viscoelastic law only (ensure_P_field recomputes it for the
+// elastic laws where it is read).
 void constitutive_residual(Engine& e) {
   constexpr int kRedB = 20;  // red[0..18): sums of F and P; red[20]: b.b
   for (auto& c : e.C) {
@@ -694,6 +701,7 @@ void constitutive_residual(Engine& e) {
       q.Pavg[i] = e.host_red[32 * p + 9 + i] / N;
     }
     q.state_valid = true;
+    q.p_field_valid = q.kind == MAT_VISCO;
     const double bb = e.host_red[32 * p + kRedB];
     q.rms_b = std::sqrt(bb / N);
     e.hdesc[p].rr0 = bb;
@@ -1394,11 +1402,26 @@ void refresh_averages(Engine& e, int p) {
   e.P[p].status = keep;
 }
 
+// P(F) of problem p in its P field, for a reader of that field; the averages and the status
+// stay those of the last evaluation
+void ensure_P_field(Engine& e, int p) {
+  refresh_averages(e, p);
+  if (e.P[p].p_field_valid) return;
+  for (size_t i = 0; i < e.P.size(); ++i) e.hdesc[i].active = (int)i == p ? 1 : 0;
+  upload_descs(e);
+  const int keep = e.P[p].status;
+  const std::string keep_msg = e.P[p].msg;
+  constitutive(e, false);
+  if (!e.P[p].state_valid) fail(GHOM_EDOMAIN, "det F <= 0 at some voxel");
+  e.P[p].status = keep;
+  e.P[p].msg = keep_msg;
+}
+
 void copy_field(Engine& e, int p, int which, double* dst, hipMemcpyKind kind) {
   if (which != GHOM_FIELD_F && which != GHOM_FIELD_P) fail(GHOM_EINVAL, "bad field request");
   if (which == GHOM_FIELD_P) {
     check_material(e.P[p]);
-    refresh_averages(e, p);
+    ensure_P_field(e, p);
   }
   sync(e);
   const size_t bytes = 9 * (size_t)e.C[e.P[p].cls].g.N * sizeof(double);

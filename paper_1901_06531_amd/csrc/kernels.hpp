@@ -1028,7 +1028,7 @@ struct ZfwdArgs {
   const CGScalars* sc;        // early exit / beta (nullable)
   // Z_CONST_*
   const double* F;            // deformation gradient
-  double* P;                  // stress out
+  double* P;                  // stress out (viscoelastic law only)
   TIN* state_out;             // tangent state out
   const double* scale;        // per-voxel modulus scale (nullable)
   const double* mat;          // per-phase material table (float64)
@@ -1212,9 +1212,15 @@ __device__ __forceinline__ void zfwd_body(const Geo& g, const ZfwdArgs<T, TIN>& 
         if (!constitutive_point<TIN, KIND>(f, args.phase[vox], sv, args.scale != nullptr, args.mat, pv, args.state_out,
                                            g.N, vox, args.iv))
           bad = 1;
+        // the elastic laws' P field is not stored: it is a function of F, recomputed where it
+        // is read; the viscoelastic law's P depends on internal variables that the increment's
+        // commit replaces, so its P field is stored here
+        if constexpr (MODE == Z_CONST_VISCO) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) st_s<kNT>(&args.P[c * g.N + vox], pv[c]);
+        }
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-          st_s<kNT>(&args.P[c * g.N + vox], pv[c]);
           val[c] = (T)pv[c];
           cs[c] += f[c];
           cs[9 + c] += pv[c];

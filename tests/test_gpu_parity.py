@@ -256,6 +256,46 @@ def test_mixed_particles_history_matches_oracle():
     assert np.max(np.abs(Fg - o.F)) < 1e-9
 
 
+@pytest.mark.parametrize("law", ["nh", "svk"])
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_stress_field_after_steps_is_P_of_F(law, prec):
+    """The Newton iteration of the elastic laws keeps only the transform and the average of P;
+    the P field read after an increment is P(F) of the F field (the oracle's law at 1e-13),
+    and reading it leaves the averages of the last evaluation as they were, bit for bit."""
+    say("P field on request", law, prec)
+    if law == "nh":
+        w = synth.workload_particles(n=16, seed=2, count=4, nsteps=10)
+    else:
+        w = synth.workload_polycrystal(n=16, ngrains=8)
+    o = go.Oracle(w["shape"])
+    if law == "nh":
+        o.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+    else:
+        o.set_material_svk(w["phase"], w["C"])
+    if w.get("scale") is not None:
+        o.set_stiffness_scale(w["scale"])
+    with ghom.Solver(w["shape"], precision=prec) as s:
+        s.setup(w)
+        s.set_tolerances(w["newton_tol"], w["cg_tol"], 0.0 if prec == ghom.FP64 else 1e-5)
+        for _ in range(2):
+            s.step()
+        F0, P0 = s.averages()
+        P = s.field(ghom.FIELD_P)
+        F1, P1 = s.averages()
+        Pd = s.field_device(ghom.FIELD_P).cpu().numpy()
+        F = s.field(ghom.FIELD_F)
+        s.step()  # the iteration goes on from the same state
+        F2, P2 = s.averages()
+        P3 = s.field(ghom.FIELD_P)
+        F3 = s.field(ghom.FIELD_F)
+    assert np.array_equal(F0, F1) and np.array_equal(P0, P1)
+    assert np.array_equal(P, Pd)
+    assert rel_err(P, o.stress(F)) < 1e-13
+    assert np.max(np.abs(P.reshape(9, -1).mean(axis=1) - P0)) < 1e-13 * max(1.0, np.abs(P0).max())
+    assert rel_err(P3, o.stress(F3)) < 1e-13
+    assert not np.array_equal(F2, F0)
+
+
 def test_svk_polycrystal_matches_oracle():
     """Small rotated-cubic SVK polycrystal under full stress control."""
     say("polycrystal16 svk fp64")
