@@ -138,7 +138,7 @@ struct Engine {
   bool graphs = false;  // replay captured HIP graphs of CG iterations (not while profiling)
   bool checkpoints = false;  // keep per-increment states of path-dependent laws (adjoint)
   bool rot_gauge = true;     // rotation gauge of full stress control (control.hpp)
-  std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, first-iteration flag, iterations
+  std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, start mode, first-iteration flag, iterations
   bool prof = false;
   std::string prof_only;  // time only launches of this name (empty: all)
   std::map<std::string, ProfRec> prof_recs;
@@ -573,7 +573,8 @@ void launch_sum_columns(Engine& e, const int* ids, int np, int nparts, int K, in
 }
 
 // out = scale * G*(in - Pbar) in float64 for every active problem of a class
-// role: ROLE_RESID (P -> b, with b.b partials), ROLE_REPROJ (x -> dF64), ROLE_PROJ (in -> out),
+// role: ROLE_RESID (P -> b, with b.b partials), ROLE_RESID_R (the same into r in the CG type),
+// ROLE_REPROJ (x -> dF64), ROLE_PROJ (in -> out),
 // ROLE_NEWTON (F += G*(x), Newton-update partials)
 int project64(Engine& e, ShapeClass& c, int role, const std::string& tag) {
   const std::string pre = tag + "_";
@@ -587,7 +588,8 @@ int project64(Engine& e, ShapeClass& c, int role, const std::string& tag) {
 
 // A(v) = G*(K : v) in the CG type.  ROLE_OP_CG: one CG step (see the kernels); returns the
 // z-pass grid (the partial count of its reductions).  ROLE_OP_PLAIN: in -> out.
-// update_p: 0 p as is, 1 p <- r + beta p, 2 CG start (r = p = b, x not read)
+// update_p: 0 p as is, 1 p <- r + beta p, 2 CG start (r = p = b, x not read), 3 CG start
+// from r (p = r: the Newton residual was written into r)
 template <typename T>
 int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
   const std::string t = tname<T>();
@@ -596,7 +598,7 @@ int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
   else if (c.kind == MAT_SVK) gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
   else gz = launch_zfwd<T, Z_VISCO, T>(e, c, role, update_p, "op_zfwd_" + t);
   middle_passes<T>(e, c, role, "op_", role == ROLE_OP_CG ? gz : 0);
-  if (role == ROLE_OP_CG) launch_zinv<T, T, ZI_CG>(e, c, role, "op_zinv_" + t, update_p == 2 ? 1 : 0);
+  if (role == ROLE_OP_CG) launch_zinv<T, T, ZI_CG>(e, c, role, "op_zinv_" + t, update_p >= 2 ? 1 : 0);
   else launch_zinv<T, T, ZI_PLAIN>(e, c, role, "op_zinv_" + t);
   return gz;
 }
@@ -672,20 +674,23 @@ void constitutive_residual(Engine& e) {
     HIPCALL(hipGetLastError());
     int gz = 0;
     if (c.kind == MAT_NH) {
-      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_NH, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
-      else gz = launch_zfwd<double, Z_CONST_NH, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_NH, double>(e, c, ROLE_RESID_R, 0, "res_zfwd_f64");
+      else gz = launch_zfwd<double, Z_CONST_NH, float>(e, c, ROLE_RESID_R, 0, "res_zfwd_f64");
     } else if (c.kind == MAT_SVK) {
-      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_SVK, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
-      else gz = launch_zfwd<double, Z_CONST_SVK, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_SVK, double>(e, c, ROLE_RESID_R, 0, "res_zfwd_f64");
+      else gz = launch_zfwd<double, Z_CONST_SVK, float>(e, c, ROLE_RESID_R, 0, "res_zfwd_f64");
     } else {
-      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_VISCO, double>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
-      else gz = launch_zfwd<double, Z_CONST_VISCO, float>(e, c, ROLE_RESID, 0, "res_zfwd_f64");
+      if (e.prec == GHOM_FP64) gz = launch_zfwd<double, Z_CONST_VISCO, double>(e, c, ROLE_RESID_R, 0, "res_zfwd_f64");
+      else gz = launch_zfwd<double, Z_CONST_VISCO, float>(e, c, ROLE_RESID_R, 0, "res_zfwd_f64");
     }
     timed(e, "reduce", [&] {
       launch_sum_columns(e, c.ids, np, gz, 18, 0, 1, 0, 1);
     });
-    middle_passes<double>(e, c, ROLE_RESID, "res_");
-    const int gi = launch_zinv<double, double, ZI_PLAIN>(e, c, ROLE_RESID, "res_zinv_f64");
+    middle_passes<double>(e, c, ROLE_RESID_R, "res_");
+    // b = -G*(P - Pbar) goes straight into the CG residual r in the CG type (the solve starts
+    // from it with p = r); its square sum is taken before the narrowing store
+    const int gi = e.prec == GHOM_FP64 ? launch_zinv<double, double, ZI_PLAIN>(e, c, ROLE_RESID_R, "res_zinv_f64")
+                                       : launch_zinv<double, float, ZI_PLAIN>(e, c, ROLE_RESID_R, "res_zinv_f64");
     timed(e, "reduce", [&] {
       launch_sum_columns(e, c.ids, np, gi, 1, 0, 0, kRedB, 0);
     });
@@ -717,9 +722,10 @@ void constitutive_residual(Engine& e) {
 // Conjugate gradients on A dF = b from dF = 0 for every active problem; the stop test of
 // each problem is set in its descriptor (cg_thresh, max_cg).  Returns when all are done.
 // finish: apply the step of the last completed iteration to x here (the Newton update, which
-// reads x anyway, applies it itself and passes false)
+// reads x anyway, applies it itself and passes false).  rhs_in_r: b is already in r (in the CG
+// type), as the Newton residual writes it; else it is read from the float64 buffer b.
 template <typename T>
-void cg_solve(Engine& e, double* t_ms, bool finish = true) {
+void cg_solve(Engine& e, double* t_ms, bool finish = true, bool rhs_in_r = false) {
   const auto t0 = std::chrono::steady_clock::now();
   long long vox = 0;
   for (auto& c : e.C) {
@@ -746,7 +752,7 @@ void cg_solve(Engine& e, double* t_ms, bool finish = true) {
     for (int i = 0; i < k; ++i) {
       for (auto& c : e.C) {
         if (!all_classes && !class_active(e, c)) continue;
-        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, (first && i == 0) ? 2 : 1);
+        const int gz = operator_apply<T>(e, c, ROLE_OP_CG, (first && i == 0) ? (rhs_in_r ? 3 : 2) : 1);
         timed(e, "cg_beta", [&] {
           hipLaunchKernelGGL(cg_beta_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
                              c.ids, gz);
@@ -757,7 +763,8 @@ void cg_solve(Engine& e, double* t_ms, bool finish = true) {
   auto enqueue_chunk = [&](int k) {
     const bool first = enqueued == 0;
     if (e.graphs && !e.prof) {
-      const long long key = ((long long)sizeof(T) << 40) | ((long long)first << 32) | (long long)k;
+      const long long key = ((long long)sizeof(T) << 40) | ((long long)rhs_in_r << 33) | ((long long)first << 32) |
+                            (long long)k;
       auto it = e.graph_cache.find(key);
       if (it == e.graph_cache.end()) {
         hipGraph_t g = nullptr;
@@ -912,8 +919,9 @@ void newton(Engine& e, const std::vector<int>& set) {
     set_active_from_running(e, set);
     if (!any_running(e, set)) break;
     double tcg = 0.0;
-    if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg, false);  // newton_update applies the pending step
-    else cg_solve<float>(e, &tcg, false);
+    // newton_update applies the pending step; the residual left the right-hand side in r
+    if (e.prec == GHOM_FP64) cg_solve<double>(e, &tcg, false, true);
+    else cg_solve<float>(e, &tcg, false, true);
     for (int p : set) {
       Prob& q = e.P[p];
       if (!q.running) continue;

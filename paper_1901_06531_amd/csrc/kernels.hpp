@@ -1017,7 +1017,8 @@ struct ZfwdArgs {
   int x_mode;                 // update_p == 1: 1 x <- alpha p (x not yet written), 2 x <- x + alpha p
   T alpha;                    // the previous CG step's alpha
   const double* b;            // update_p == 2: the Newton right-hand side
-  int update_p;               // 0: p as is; 1: x <- x + alpha p, p <- r + beta p; 2 (CG start): r <- b, p <- b
+  int update_p;               // 0: p as is; 1: x <- x + alpha p, p <- r + beta p; 2 (CG start): r <- b, p <- b;
+                              // 3 (CG start, right-hand side already in r): p <- r
   const T* state;             // tangent state planes
   const uint16_t* phase;      // SVK: phase of each voxel
   const T* C6;                // SVK: per-phase 6x6 Voigt stiffness in the CG type
@@ -1083,6 +1084,11 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
       for (int k = 0; k < SD; ++k)
 #pragma unroll
         for (int c = 0; c < 9; ++c) dv[k][c] = (T)ld_s<kNT>(&args.b[c * N + vx[k]]);
+    } else if (args.update_p == 3) {
+#pragma unroll
+      for (int k = 0; k < SD; ++k)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dv[k][c] = ld_s<kNT>(&args.r[c * N + vx[k]]);
     } else if (args.update_p == 1) {
       // the CG iterate takes the previous step's alpha p here, where p is read anyway (so the
       // inverse pass reads neither x nor p); p <- r + beta p
@@ -1138,7 +1144,7 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
             st_s<kNT>(&args.r[c * N + vx[k]], d[c]);
             st_s<kNT>(&args.p[c * N + vx[k]], d[c]);
           }
-        } else if (args.update_p == 1) {
+        } else if (args.update_p == 1 || args.update_p == 3) {
 #pragma unroll
           for (int c = 0; c < 9; ++c) st_s<kNT>(&args.p[c * N + vx[k]], d[c]);
         }
@@ -1449,9 +1455,9 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
     const int pair = lp >> 1, part = lp & 1;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
-      st_s<kNT>(&args.out[c * g.N + vox], o);
-      if (args.self_dot) acc += (double)o * (double)o;
+      const T o = ldsr[2 * ((c * LP + pair) * R + z) + part];
+      st_s<kNT>(&args.out[c * g.N + vox], (TOUT)o);
+      if (args.self_dot) acc += (double)o * (double)o;  // of the value before a narrowing store
     }
   }
   if constexpr (ZM == ZI_NEWTON) {
@@ -1672,7 +1678,9 @@ enum {
   ROLE_REPROJ = 3,    // G*(x) into dF64 (float64)
   ROLE_PROJ = 4,      // G*(in) into out (float64)
   ROLE_NEWTON = 5,    // F += G*(x) (float64) with the Newton-update partials
-  ROLE_ADJ = 6        // G*(in) into b (float64) with b.b partials: an adjoint right-hand side
+  ROLE_ADJ = 6,       // G*(in) into b (float64) with b.b partials: an adjoint right-hand side
+  ROLE_RESID_R = 7    // -G*(P - P-bar) into r (the CG type) with b.b partials: the Newton
+                      // right-hand side where the solve starts from it (CG start mode 3)
 };
 
 struct ProbDesc {
@@ -1710,12 +1718,14 @@ template <typename T> __device__ __forceinline__ const cx<T>* twd(const ProbDesc
 template <> __device__ __forceinline__ const cx<double>* twd<double>(const ProbDesc& d, int axis) { return d.tw64[axis]; }
 template <> __device__ __forceinline__ const cx<float>* twd<float>(const ProbDesc& d, int axis) { return d.tw32[axis]; }
 
+__device__ __forceinline__ bool resid_role(int role) { return role == ROLE_RESID || role == ROLE_RESID_R; }
+
 __device__ __forceinline__ ProjParams proj_params(const ProbDesc& d, int role) {
   ProjParams pp;
   pp.mask = d.mask;
   const double n = (double)d.g.N;
-  pp.post = (role == ROLE_RESID ? -1.0 : 1.0) / n;
-  pp.pbar = role == ROLE_RESID ? d.pbar : nullptr;
+  pp.post = (resid_role(role) ? -1.0 : 1.0) / n;
+  pp.pbar = resid_role(role) ? d.pbar : nullptr;
   pp.n = n;
   return pp;
 }
@@ -1739,7 +1749,7 @@ zfwd_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
     a.partials = d.partials;
     a.pstride = (int)gridDim.x;
   } else if constexpr (MODE == Z_PLAIN) {
-    a.in = role == ROLE_RESID ? reinterpret_cast<const TIN*>(d.P)
+    a.in = resid_role(role) ? reinterpret_cast<const TIN*>(d.P)
                               : ((role == ROLE_REPROJ || role == ROLE_NEWTON) ? reinterpret_cast<const TIN*>(d.x)
                                                      : reinterpret_cast<const TIN*>(d.in));
     if (role == ROLE_NEWTON) {  // the Newton correction: the CG iterate with the solve's pending step
@@ -1854,10 +1864,11 @@ zinv_batch(const ProbDesc* __restrict__ D, const int* __restrict__ ids, int role
     a.F = d.F;
     a.pstride = (int)gridDim.x;
   } else {
-    a.out = (role == ROLE_RESID || role == ROLE_ADJ)
+    a.out = role == ROLE_RESID_R ? reinterpret_cast<TOUT*>(d.r)
+            : (role == ROLE_RESID || role == ROLE_ADJ)
                 ? reinterpret_cast<TOUT*>(d.b)
                 : (role == ROLE_REPROJ ? reinterpret_cast<TOUT*>(d.dF64) : reinterpret_cast<TOUT*>(d.out));
-    a.self_dot = role == ROLE_RESID || role == ROLE_ADJ;
+    a.self_dot = resid_role(role) || role == ROLE_ADJ;
   }
   zinv_body<T, A, B, TOUT, ZM, NTS>(d.g, a, blockIdx.x);
 }
