@@ -121,6 +121,14 @@ struct Engine {
   std::vector<ShapeClass> C;
   ProbDesc* hdesc = nullptr;  // pinned host mirror
   ProbDesc* ddesc = nullptr;
+  // descriptor uploads without a stream synchronisation: the mirror is staged in a ring of
+  // pinned slots, each reused after its copy has completed; an unchanged mirror is not sent
+  static constexpr int kDescSlots = 4;
+  ProbDesc* desc_stage[kDescSlots] = {};
+  hipEvent_t desc_ev[kDescSlots] = {};
+  bool desc_pending[kDescSlots] = {};
+  int desc_next = 0;
+  std::vector<ProbDesc> desc_sent;  // what the device holds (empty: not known)
   char* arena = nullptr;
   size_t np = 0;              // partials per problem
   CGScalars* sc = nullptr;    // device, one per problem
@@ -220,9 +228,25 @@ int vox_blocks(long long n) {
   return (int)std::max(1LL, std::min<long long>(b, kMaxVoxBlocks));
 }
 
+// The device descriptors take the host mirror's values for every kernel enqueued after this
+// call; the host may change the mirror again at once.
 void upload_descs(Engine& e) {
-  HIPCALL(hipMemcpyAsync(e.ddesc, e.hdesc, e.P.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, e.stream));
-  sync(e);
+  const size_t n = e.P.size();
+  const size_t bytes = n * sizeof(ProbDesc);
+  if (!e.desc_stage[0]) {  // no staging slots (a one-call engine): copy, then wait
+    HIPCALL(hipMemcpyAsync(e.ddesc, e.hdesc, bytes, hipMemcpyHostToDevice, e.stream));
+    sync(e);
+    return;
+  }
+  if (e.desc_sent.size() == n && std::memcmp(e.desc_sent.data(), e.hdesc, bytes) == 0) return;
+  const int k = e.desc_next;
+  e.desc_next = (k + 1) % Engine::kDescSlots;
+  if (e.desc_pending[k]) HIPCALL(hipEventSynchronize(e.desc_ev[k]));
+  std::memcpy(e.desc_stage[k], e.hdesc, bytes);
+  HIPCALL(hipMemcpyAsync(e.ddesc, e.desc_stage[k], bytes, hipMemcpyHostToDevice, e.stream));
+  HIPCALL(hipEventRecord(e.desc_ev[k], e.stream));
+  e.desc_pending[k] = true;
+  e.desc_sent.assign(e.hdesc, e.hdesc + n);
 }
 
 bool class_active(Engine& e, const ShapeClass& c) {
@@ -1145,6 +1169,10 @@ void destroy_engine(Engine* e) {
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (e->hdesc) (void)hipHostFree(e->hdesc);
+  for (int k = 0; k < Engine::kDescSlots; ++k) {
+    if (e->desc_stage[k]) (void)hipHostFree(e->desc_stage[k]);
+    if (e->desc_ev[k]) (void)hipEventDestroy(e->desc_ev[k]);
+  }
   if (e->host_sc) (void)hipHostFree(e->host_sc);
   if (e->host_red) (void)hipHostFree(e->host_red);
   for (auto& kv : e->prof_recs)
@@ -1231,6 +1259,10 @@ void build_engine(Engine& e, const std::vector<ProbSpec>& specs, const std::vect
   HIPCALL(hipMalloc((void**)&e.sc, n * sizeof(CGScalars)));
   HIPCALL(hipMalloc((void**)&e.flags, n * sizeof(int)));
   HIPCALL(hipHostMalloc((void**)&e.hdesc, n * sizeof(ProbDesc), hipHostMallocDefault));
+  for (int k = 0; k < Engine::kDescSlots; ++k) {
+    HIPCALL(hipHostMalloc((void**)&e.desc_stage[k], n * sizeof(ProbDesc), hipHostMallocDefault));
+    HIPCALL(hipEventCreateWithFlags(&e.desc_ev[k], hipEventDisableTiming));
+  }
   // coherent mapped memory: the CG kernels' stores reach the host without a copy
   HIPCALL(hipHostMalloc((void**)&e.host_sc, n * sizeof(CGScalars), hipHostMallocMapped | hipHostMallocCoherent));
   HIPCALL(hipHostGetDevicePointer((void**)&e.host_sc_dev, e.host_sc, 0));
@@ -2000,6 +2032,7 @@ int ghom_adjoint_grad_scale(ghom_ctx* c, const double a[9], double* grad_out) {
     HIPCALL(hipMalloc((void**)&grad_dev, (size_t)N * sizeof(double)));
     e.hdesc[0].out = grad_dev;
     const hipError_t ue = hipMemcpyAsync(e.ddesc, e.hdesc, sizeof(ProbDesc), hipMemcpyHostToDevice, e.stream);
+    e.desc_sent.clear();  // the device copy differs from the last upload's
     if (ue == hipSuccess)
       hipLaunchKernelGGL(adjoint_grad_batch, dim3(cl.vb, 1, 1), dim3(kVoxThreads), 0, e.stream, e.ddesc, cl.ids);
     const hipError_t le = hipGetLastError();
