@@ -1065,6 +1065,11 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
   constexpr bool kNT = NTS;  // nontemporal streamed accesses
   constexpr int IT = (2 * LP * NZ + NT - 1) / NT;
   constexpr int KS = MODE == Z_NH ? kNHState : (MODE == Z_SVK ? 9 : 15);
+  // with one thread per z (NT == NZ) item k of a thread is line k at z = threadIdx.x, so a
+  // chunk of an even number of items holds whole line pairs: each component goes to LDS as one
+  // complex store (re: line 2m, im: line 2m + 1) instead of two real stores 8 B apart, which
+  // take two passes through the LDS banks
+  constexpr bool kLdsPairs = NT == NZ && SD % 2 == 0 && IT % SD == 0;
   const long long N = g.N;
   double pkp = 0.0;
 #pragma unroll
@@ -1130,12 +1135,13 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
         sv[k] = args.has_scale ? ld_s<kNT>(&args.state[KS * N + vx[k]]) : (T)1;
       }
     }
+    T pv[kLdsPairs ? SD : 1][9];  // kLdsPairs: the chunk's values, stored a line pair at a time
 #pragma unroll
     for (int k = 0; k < SD; ++k) {
       const int t = threadIdx.x + (c0 + k) * NT;
       if (c0 + k >= IT || t >= 2 * LP * NZ) break;
       const int lp = t / NZ, z = t - lp * NZ;
-      T val[9];
+      T* val = pv[kLdsPairs ? k : 0];
       if (ok[k]) {
         const T* d = dv[k];
         if (args.update_p == 2) {
@@ -1159,9 +1165,20 @@ __device__ __forceinline__ double zfwd_cg_fill(const Geo& g, const ZfwdArgs<T, T
 #pragma unroll
         for (int c = 0; c < 9; ++c) val[c] = 0;
       }
-      const int pair = lp >> 1, part = lp & 1;
+      if constexpr (!kLdsPairs) {
+        const int pair = lp >> 1, part = lp & 1;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * R + z) + part] = val[c];
+        for (int c = 0; c < 9; ++c) ldsr[2 * ((c * LP + pair) * R + z) + part] = val[c];
+      }
+    }
+    if constexpr (kLdsPairs) {
+#pragma unroll
+      for (int k = 0; k < SD; k += 2) {
+        const int pair = (c0 + k) >> 1;  // lines c0 + k and c0 + k + 1 at z = threadIdx.x
+        cx<T>* L = reinterpret_cast<cx<T>*>(ldsr);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) L[(c * LP + pair) * R + threadIdx.x] = cx<T>{pv[k][c], pv[k + 1][c]};
+      }
     }
   }
   return pkp;
@@ -1405,6 +1422,23 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
 #pragma unroll
           for (int c = 0; c < 9; ++c) rv[k][c] = ld_s<kNT>(&args.r[c * N + v]);
         }
+        // one thread per z (NT == NZ): a chunk of an even number of items holds whole line
+        // pairs, read from LDS as one complex value per component (see zfwd_cg_fill)
+        constexpr bool kLdsPairs = NT == NZ && SD % 2 == 0 && IT % SD == 0;
+        T lv[kLdsPairs ? SD : 1][9];
+        if constexpr (kLdsPairs) {
+          const cx<T>* L = reinterpret_cast<const cx<T>*>(ldsr);
+#pragma unroll
+          for (int k = 0; k < SD; k += 2) {
+            const int pair = (c0 + k) >> 1;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+              const cx<T> w = L[(c * LP + pair) * R + threadIdx.x];
+              lv[k][c] = w.re;
+              lv[k + 1][c] = w.im;
+            }
+          }
+        }
 #pragma unroll
         for (int k = 0; k < SD; ++k) {
           const int it = c0 + k;
@@ -1415,7 +1449,7 @@ __device__ __forceinline__ void zinv_body(const Geo& g, const ZinvArgs<T, TOUT>&
           const int pair = lp >> 1, part = lp & 1;
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            const TOUT o = (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
+            const TOUT o = kLdsPairs ? (TOUT)lv[kLdsPairs ? k : 0][c] : (TOUT)ldsr[2 * ((c * LP + pair) * R + z) + part];
             const TOUT rn = rv[k][c] - alpha * o;
             st_s<kNT>(&args.r[c * N + vx[it]], rn);
             acc += (double)rn * (double)rn;
