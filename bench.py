@@ -493,6 +493,8 @@ def main():
                    "newton_tol": w["newton_tol"], "cg_tol": w["cg_tol"], "cg_forcing": CG_FORCING},
         "newton_step_ms": round(split["newton_step_ms"], 3),
         "cg_ms_per_iter": round(split["cg_ms_per_iter"], 4),
+        # the rate inside the CG loops alone (operator, update and reductions; no Newton level)
+        "cg_loop_voxel_iters_per_s": round(N / (split["cg_ms_per_iter"] * 1e-3), 1),
         "cg_iters": split["cg_iters"],
         "newton_iters": split["newton_iters"],
         "newton_per_increment": split["newton_per_increment"],
@@ -507,6 +509,7 @@ def main():
         "fp64": None if fp64 is None else {
             "value": round(fp64["voxel_iters_per_s"], 1), "ms_per_step": round(fp64["ms_per_increment"], 3),
             "newton_step_ms": round(fp64["newton_step_ms"], 3), "cg_ms_per_iter": round(fp64["cg_ms_per_iter"], 4),
+            "cg_loop_voxel_iters_per_s": round(N / (fp64["cg_ms_per_iter"] * 1e-3), 1),
             "cg_iters": fp64["cg_iters"], "newton_iters": fp64["newton_iters"],
             "cg_stalls": fp64["cg_stalls"], "failures": fp64["failures"],
             "split_vs_fp64_F11_diff": abs(fp64["F11"] - split["F11"])},

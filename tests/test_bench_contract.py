@@ -51,6 +51,8 @@ def test_json_line_has_the_contract_fields():
         assert key in d, key
     assert d["n_gpus"] == 1 and d["steps"] == 1 and d["warmup"] == 1
     assert d["value"] > 0 and d["ms_per_step"] > 0 and d["higher_is_better"] is True
+    # the CG loops alone run faster than whole increments (which add the Newton level)
+    assert d["cg_loop_voxel_iters_per_s"] > d["value"]
     assert d["vs_baseline"] is None and d["cpu_baseline"] is None  # --no-cpu
     assert d["config"]["workload"] == "polycrystal32_svk_stress" and d["config"]["grid"] == [32, 32, 32]
     roof = d["roofline"]

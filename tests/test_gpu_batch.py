@@ -99,3 +99,29 @@ def test_batch_problem_matches_oracle():
         F, P = o.averages()
         np.testing.assert_allclose(got[i][0], F, rtol=0, atol=1e-10)
         np.testing.assert_allclose(got[i][1], P, rtol=0, atol=1e-10)
+
+
+def test_batch_stress_field_is_P_of_F():
+    """The stress field of a batch problem, read after its increments, is P(F) of its F field
+    (computed on request for the elastic laws) and reading it leaves every problem's averages
+    as they were."""
+    ws = _problems()
+    with ghom.Batch(ws, precision=ghom.FP32_SPLIT) as b:
+        b.set_tolerances(1e-10, 1e-11, 1e-5)
+        for _ in range(2):
+            b.step()
+        before = [b.averages(i) for i in range(len(ws))]
+        got = {i: (b.field(i, ghom.FIELD_F), b.field(i, ghom.FIELD_P)) for i in (1, 4)}
+        after = [b.averages(i) for i in range(len(ws))]
+    for (F0, P0), (F1, P1) in zip(before, after):
+        assert np.array_equal(F0, F1) and np.array_equal(P0, P1)
+    for i, (F, P) in got.items():
+        w = ws[i]
+        o = go.Oracle(w["shape"])
+        if w["kind"] == "svk":
+            o.set_material_svk(w["phase"], w["C"])
+        else:
+            o.set_material_neohookean(w["phase"], w["mu"], w["lam"])
+        ref = o.stress(F)
+        say("  problem", i, w["kind"], "max |P - P(F)|", float(np.max(np.abs(P - ref))))
+        assert np.max(np.abs(P - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
