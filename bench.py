@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "CG operator voxel-iters/s + Newton step time at 256^3, FP64 vs FP32-split"
 PEAK_HBM_GBS = 8000.0
 CG_FORCING = 1e-5
+# the timed region brackets every PROFILE_EVERY-th launch of the dominant kernel with HIP
+# events (each bracketed launch leaves the GPU idle for a few microseconds); a uniform sample
+PROFILE_EVERY = 4
 
 
 def log(*a):
@@ -106,8 +109,8 @@ def run_gpu(w, precision, steps, warmup, profile):
     # floor, and the float64 run uses the same rule so that the two are compared fairly
     s.set_tolerances(w["newton_tol"], w["cg_tol"], CG_FORCING)
     # warm-up: every launch timed, to find the operator pass with the largest share; the
-    # timed region then brackets only that kernel with events (each timed launch costs a
-    # few microseconds)
+    # timed region then brackets only every PROFILE_EVERY-th launch of that kernel with events
+    # (each timed launch costs a few microseconds)
     if profile and warmup:
         s.profile_reset()
         s.set_profiling(True)
@@ -147,6 +150,7 @@ def run_gpu(w, precision, steps, warmup, profile):
             keep, _, _ = steady_launches(s.profile_samples(k))
             warm_steady[k] = float(keep.mean())
         s.set_profiling_filter(max(op, key=lambda k: op[k][1]) if op else None)
+        s.set_option(ghom.OPT_PROFILE_EVERY, PROFILE_EVERY)
     import torch
     torch.cuda.synchronize()
     if profile:
@@ -456,8 +460,8 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, w["shape"]),
                 "kernel": name,
                 "avg_ms": round(avg_ms, 4), "bytes_per_launch": per_launch,
-                "launches": {"steady": int(len(keep)), "noop": noop, "other": other,
-                             "all_avg_ms": round(ms / launches, 4)}}
+                "launches": {"sampled_every": PROFILE_EVERY, "steady": int(len(keep)), "noop": noop,
+                             "other": other, "all_avg_ms": round(ms / launches, 4)}}
         log("kernel times (timed region): " + ", ".join("%s %.3f ms x%d" % (k, v[1] / v[0], v[0])
                                                         for k, v in sorted(op.items())))
 

@@ -284,7 +284,11 @@ enum {
                               ghom_set_control); 0: the mask exactly as set.  Takes effect at
                               the next solve. */
   GHOM_OPT_YPASS_F64 = 8,  /* y-pass (transform along y) variant, float64                   */
-  GHOM_OPT_YPASS_F32 = 9   /* the same for the float32 transforms of GHOM_FP32_SPLIT         */
+  GHOM_OPT_YPASS_F32 = 9,  /* the same for the float32 transforms of GHOM_FP32_SPLIT         */
+  GHOM_OPT_PROFILE_EVERY = 10 /* k >= 1 (default 1): with profiling on (ghom_set_profiling),
+                              bracket only every k-th launch of each timed kernel name with
+                              events; each bracketed launch costs a few microseconds of idle
+                              GPU.  Setting it restarts the count. */
 };
 
 /* Selects a kernel variant.  For the x-pass keys: 0 = pick the fastest variant by timing

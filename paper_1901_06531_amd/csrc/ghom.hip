@@ -149,6 +149,8 @@ struct Engine {
   std::map<long long, hipGraphExec_t> graph_cache;  // key: CG type size, start mode, first-iteration flag, iterations
   bool prof = false;
   std::string prof_only;  // time only launches of this name (empty: all)
+  int prof_every = 1;     // time every prof_every-th launch of each timed name
+  std::map<std::string, long long> prof_seen;  // launches of each timed name so far
   std::map<std::string, ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   std::string err;
@@ -191,6 +193,11 @@ hipEvent_t get_event(Engine& e) {
 template <typename L>
 void timed(Engine& e, const std::string& name, L&& launch) {
   if (!e.prof || (!e.prof_only.empty() && name != e.prof_only)) {
+    launch();
+    HIPCALL(hipGetLastError());
+    return;
+  }
+  if (e.prof_every > 1 && e.prof_seen[name]++ % e.prof_every != 0) {
     launch();
     HIPCALL(hipGetLastError());
     return;
@@ -2168,6 +2175,12 @@ static int set_option(Engine& e, int key, int value) {
     drop_graphs(e);
     return GHOM_OK;
   }
+  if (key == GHOM_OPT_PROFILE_EVERY) {
+    if (value < 1 || value > 1000000) fail(GHOM_EINVAL, "profiling stride must be in [1, 1000000]");
+    e.prof_every = value;
+    e.prof_seen.clear();
+    return GHOM_OK;
+  }
   if (key == GHOM_OPT_ROTATION_GAUGE) {
     if (value != 0 && value != 1) fail(GHOM_EINVAL, "rotation gauge option must be 0 or 1");
     e.rot_gauge = value != 0;
@@ -2189,6 +2202,7 @@ static int get_option(Engine& e, int key, int* value) {
   else if (key == GHOM_OPT_ROTATION_GAUGE) *value = e.rot_gauge ? 1 : 0;
   else if (key == GHOM_OPT_YPASS_F64) *value = e.C[0].ypass_var[0];
   else if (key == GHOM_OPT_YPASS_F32) *value = e.C[0].ypass_var[1];
+  else if (key == GHOM_OPT_PROFILE_EVERY) *value = e.prof_every;
   else fail(GHOM_EINVAL, "unknown option");
   return GHOM_OK;
 }
@@ -2315,6 +2329,7 @@ int ghom_profile_reset(ghom_ctx* c) {
   return guard(c, [&]() -> int {
     prof_collect(*c->e);
     c->e->prof_recs.clear();
+    c->e->prof_seen.clear();
     return GHOM_OK;
   });
 }

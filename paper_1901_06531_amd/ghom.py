@@ -28,6 +28,7 @@ OPT_STREAM_NT = 6
 OPT_ROTATION_GAUGE = 7
 OPT_YPASS_F64 = 8
 OPT_YPASS_F32 = 9
+OPT_PROFILE_EVERY = 10
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONVERGED", -5: "ESINGULAR",
           -6: "EDOMAIN", -7: "ESTATE"}

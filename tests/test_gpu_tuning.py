@@ -69,3 +69,33 @@ def test_tuning_cache_file(tmp_path):
     assert second[1].split()[0] == "2"
     assert "f64: x groups 4x4 (tuned)" in second[0]
     assert first[0].split(";")[0] == second[0].split(";")[0]
+
+
+def test_profiling_stride_times_every_kth_launch():
+    """GHOM_OPT_PROFILE_EVERY = k brackets every k-th launch of a timed kernel name: the same
+    increment (same iteration counts) yields about a third of the samples with k = 3 (the CG
+    iterations queued after a solve has stopped, which exit at once, vary in number with the
+    host's timing, so the launch totals differ by a few)."""
+    from paper_1901_06531_amd import synth
+    print("profiling stride", flush=True)
+    w = synth.workload_polycrystal(n=32, ngrains=8)
+    counts = {}
+    for k in (1, 3):
+        with ghom.Solver(w["shape"], precision=ghom.FP32_SPLIT) as s:
+            s.setup(w)
+            s.set_tolerances(1e-6, 1e-8, 1e-5)
+            assert s.get_option(ghom.OPT_PROFILE_EVERY) == 1
+            s.set_option(ghom.OPT_PROFILE_EVERY, k)
+            assert s.get_option(ghom.OPT_PROFILE_EVERY) == k
+            s.set_profiling_filter("op_zfwd_f32")
+            s.set_profiling(True)
+            info = s.step()
+            prof = s.profile()
+            counts[k] = (info["cg_iters_total"], prof["op_zfwd_f32"][0], len(s.profile_samples("op_zfwd_f32")))
+            with pytest.raises(ghom.GhomError):
+                s.set_option(ghom.OPT_PROFILE_EVERY, 0)
+    print("  counts", counts, flush=True)
+    (cg1, n1, m1), (cg3, n3, m3) = counts[1], counts[3]
+    assert cg1 == cg3 and n1 == m1 and n3 == m3
+    assert n1 >= cg1 and 3 * n3 >= cg3 and n3 < n1
+    assert abs(n3 - n1 / 3) <= 4
