@@ -271,6 +271,18 @@ template <int N, typename F> void with_nt(const Engine& e, F&& f) {
   else f(std::false_type{});
 }
 
+// the forward z pass's grid (its block count: the partials of its reductions)
+template <typename T, int MODE>
+int zfwd_grid(const ShapeClass& c) {
+  int grid = 0;
+  with_split(c.nz, [&](auto s) {
+    using S = decltype(s);
+    using Cfg = ZCfg<T, S::A, S::B, zfwd_ntmin<MODE>()>;
+    grid = (int)(((long long)c.nx * c.ny + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
+  });
+  return grid;
+}
+
 template <typename T, int MODE, typename TIN>
 int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::string& name) {
   int grid = 0;
@@ -621,13 +633,22 @@ int project64(Engine& e, ShapeClass& c, int role, const std::string& tag) {
 // z-pass grid (the partial count of its reductions).  ROLE_OP_PLAIN: in -> out.
 // update_p: 0 p as is, 1 p <- r + beta p, 2 CG start (r = p = b, x not read), 3 CG start
 // from r (p = r: the Newton residual was written into r)
+// part: 0 the whole operator, 1 its forward z pass only, 2 the passes after it (a CG step
+// queued in two parts, see cg_solve)
 template <typename T>
-int operator_apply(Engine& e, ShapeClass& c, int role, int update_p) {
+int operator_apply(Engine& e, ShapeClass& c, int role, int update_p, int part = 0) {
   const std::string t = tname<T>();
   int gz;
-  if (c.kind == MAT_NH) gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p, "op_zfwd_" + t);
-  else if (c.kind == MAT_SVK) gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
-  else gz = launch_zfwd<T, Z_VISCO, T>(e, c, role, update_p, "op_zfwd_" + t);
+  if (part == 2) {
+    gz = c.kind == MAT_NH ? zfwd_grid<T, Z_NH>(c) : (c.kind == MAT_SVK ? zfwd_grid<T, Z_SVK>(c) : zfwd_grid<T, Z_VISCO>(c));
+  } else if (c.kind == MAT_NH) {
+    gz = launch_zfwd<T, Z_NH, T>(e, c, role, update_p, "op_zfwd_" + t);
+  } else if (c.kind == MAT_SVK) {
+    gz = launch_zfwd<T, Z_SVK, T>(e, c, role, update_p, "op_zfwd_" + t);
+  } else {
+    gz = launch_zfwd<T, Z_VISCO, T>(e, c, role, update_p, "op_zfwd_" + t);
+  }
+  if (part == 1) return gz;
   middle_passes<T>(e, c, role, "op_", role == ROLE_OP_CG ? gz : 0);
   if (role == ROLE_OP_CG) launch_zinv<T, T, ZI_CG>(e, c, role, "op_zinv_" + t, update_p >= 2 ? 1 : 0);
   else launch_zinv<T, T, ZI_PLAIN>(e, c, role, "op_zinv_" + t);
@@ -822,19 +843,53 @@ void cg_solve(Engine& e, double* t_ms, bool finish = true, bool rhs_in_r = false
       if (e.hdesc[p].active && !hs[p].done) return false;
     return true;
   };
-  enqueue_chunk(chunk);
-  mark(0);
+  // One iteration per chunk (large problems) and no graphs: the next iteration is queued in two
+  // parts, its forward z pass before the host waits for the current iteration's flags and the
+  // passes after it once the flags say go on (the forward pass runs meanwhile), so that a
+  // solve that has stopped leaves one forward pass to return at once instead of a whole
+  // iteration.
+  const bool split = chunk == 1 && !(e.graphs && !e.prof);
+  auto launch_part = [&](bool first, int part) {
+    for (auto& c : e.C) {
+      if (!class_active(e, c)) continue;
+      const int gz = operator_apply<T>(e, c, ROLE_OP_CG, first ? (rhs_in_r ? 3 : 2) : 1, part);
+      if (part == 2)
+        timed(e, "cg_beta", [&] {
+          hipLaunchKernelGGL(cg_beta_batch, dim3((unsigned)c.probs.size()), dim3(kRedThreads), 0, e.stream, e.ddesc,
+                             c.ids, gz);
+        });
+    }
+  };
   int slot = 0;
-  for (;;) {
-    if (enqueued > it_cap + 64) fail(GHOM_EHIP, "CG stop flags not seen by the host");
-    if (chunk < 8 && vox < (1LL << 21)) chunk *= 2;
+  if (split) {
+    launch_part(true, 1);
+    launch_part(true, 2);
+    mark(0);
+    launch_part(false, 1);
+    enqueued = 1;
+    for (;;) {
+      if (enqueued > it_cap + 64) fail(GHOM_EHIP, "CG stop flags not seen by the host");
+      if (all_done(slot)) break;
+      launch_part(false, 2);
+      mark(1 - slot);
+      launch_part(false, 1);
+      enqueued += 1;
+      slot = 1 - slot;
+    }
+  } else {
     enqueue_chunk(chunk);
-    mark(1 - slot);
-    if (all_done(slot)) break;
-    slot = 1 - slot;
+    mark(0);
+    for (;;) {
+      if (enqueued > it_cap + 64) fail(GHOM_EHIP, "CG stop flags not seen by the host");
+      if (chunk < 8 && vox < (1LL << 21)) chunk *= 2;
+      enqueue_chunk(chunk);
+      mark(1 - slot);
+      if (all_done(slot)) break;
+      slot = 1 - slot;
+    }
+    // the chunk queued last returns at once; wait for it, so that the scalars are final
+    HIPCALL(hipEventSynchronize(e.sc_ev[1 - slot]));
   }
-  // the chunk queued last returns at once; wait for it, so that the scalars are final
-  HIPCALL(hipEventSynchronize(e.sc_ev[1 - slot]));
   // a problem that stopped before its first step gets x = 0
   for (auto& c : e.C)
     for (int p : c.probs)
