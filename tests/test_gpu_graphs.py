@@ -64,3 +64,18 @@ def test_batch_graph_replays_match_eager():
             assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
     for a, b in zip(Fr, Fg):
         assert np.array_equal(a, b)
+
+
+def test_large_solves_queued_in_two_parts_match_graph_replays():
+    """From 2^21 voxels on, CG steps launched one by one are queued in two parts (the forward
+    z pass ahead of the host's look at the stop flags, the other passes after it); graph
+    replays queue whole steps.  Both give the same bits."""
+    w = synth.workload_polycrystal(n=128, ngrains=64)
+    w["target"] = w["target"][:2]
+    ref, Fr = _single(w, ghom.FP32_SPLIT, 0)
+    got, Fg = _single(w, ghom.FP32_SPLIT, 1)
+    for a, b in zip(ref, got):
+        print("  newton %d cg %d" % (a[0], a[1]), flush=True)
+        assert a[0] == b[0] and a[1] == b[1]
+        assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+    assert np.array_equal(Fr, Fg)
