@@ -80,3 +80,30 @@ def test_laminate_mixed_control_matches_exact_solution(prec, tol):
     assert np.max(np.abs(F[:, :, :thick] - FA[:, :, None, None, None])) < tol
     assert np.max(np.abs(F[:, :, thick:] - FB[:, :, None, None, None])) < tol
     assert np.max(np.abs(Pa[CASE1 > 0])) < tol  # the stress-controlled components are met
+
+
+@pytest.mark.parametrize("prec,tol", PRECS)
+def test_homogeneous_cubic_svk_uniaxial_stress_matches_material_point(prec, tol):
+    """Unrotated cubic Saint Venant-Kirchhoff cell under P11 = p, every other P component 0:
+    F = diag(a, b, b) with S22 = 0 (E22 = -C12 E11 / (C11 + C12)) and a S11 = p, i.e.
+    a (a^2 - 1) / 2 (C11 - 2 C12^2 / (C11 + C12)) = p, solved as a scalar cubic."""
+    print("homogeneous cubic SVK cell, uniaxial P11 = 0.05, precision", prec, flush=True)
+    C11, C12, C44, p = 1.7, 1.2, 0.75, 0.05
+    Y = C11 - 2 * C12 ** 2 / (C11 + C12)
+    roots = np.roots([Y / 2, 0.0, -Y / 2, -p])
+    a = float(min((r.real for r in roots if abs(r.imag) < 1e-12 and r.real > 0), key=lambda r: abs(r - 1)))
+    E11 = (a * a - 1) / 2
+    b = np.sqrt(1 + 2 * (-C12 * E11 / (C11 + C12)))
+    shape = (4, 4, 4)
+    P_end = np.zeros(9)
+    P_end[0] = p
+    with ghom.Solver(shape, precision=prec) as s:
+        s.set_material_svk(np.zeros(shape, np.uint16), synth.cubic_C(C11, C12, C44).reshape(1, 81))
+        s.set_control(synth.mask_full_stress())
+        s.set_history(synth.history_stress_ramp(P_end, 2))
+        s.set_tolerances(1e-11, 1e-13, 0.0 if prec == ghom.FP64 else 1e-5)
+        for _ in range(2):
+            s.step()
+        F, P = s.averages()
+    np.testing.assert_allclose(F, [a, 0, 0, 0, b, 0, 0, 0, b], rtol=0, atol=tol)
+    np.testing.assert_allclose(P, P_end, rtol=0, atol=tol)
