@@ -308,9 +308,26 @@ def _oracle_newton_step(w):
     return time.perf_counter() - t0, its
 
 
+def _oracle_operator_s(w):
+    """Wall time of one oracle operator application A(v) = G*(K : v) on workload w at F = I
+    (v seeded random): the work of one CG iteration at the benchmark's own grid."""
+    from oracle import ghom_oracle as go
+
+    o = go.Oracle(w["shape"])
+    o.set_material_svk(w["phase"], w["C"])
+    o.set_control(w["mask"])
+    F = np.zeros((9,) + tuple(w["shape"]))
+    F[[0, 4, 8]] = 1.0
+    v = np.random.default_rng(0).standard_normal((9,) + tuple(w["shape"]))
+    t0 = time.perf_counter()
+    o.apply_operator(v, F)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(grid, seconds=15.0):
     """The FP64 oracle timed on this host (its transforms on every core): CG iterations at
-    the 128^3 and 16^3 instances of the benchmark's generator, and one Newton step at 64^3."""
+    the 128^3 and 16^3 instances of the benchmark's generator, one Newton step at 64^3, and
+    one operator application at the benchmark's grid."""
     from oracle import ghom_oracle as go
     from paper_1901_06531_amd import synth
 
@@ -318,11 +335,13 @@ def cpu_baseline(grid, seconds=15.0):
     rate, its, dt = _oracle_cg_rate(synth.workload_polycrystal(n=big), seconds)
     rate16, its16, dt16 = _oracle_cg_rate(synth.workload_polycrystal(n=16, ngrains=64), 1.0)
     nt, nits = _oracle_newton_step(synth.workload_polycrystal(n=64))
+    op_s = _oracle_operator_s(synth.workload_polycrystal(n=grid))
     return {"value": rate, "unit": "voxel-iters/s", "cores": go.WORKERS, "kind": "oracle",
             "sample": "%d CG iteration(s) of the oracle's first Newton solve on the %d^3 instance of the "
                       "benchmark's polycrystal generator (%.1f s)" % (its, big, dt),
             "cg_voxel_iters_per_s_16": rate16,
             "newton_step_s_64": round(nt, 3),
+            "operator_s_%d" % grid: round(op_s, 3),
             "newton_step_sample": "one oracle Newton iteration (constitutive update, FP64 residual, CG solve of "
                                   "%d iterations at forcing 1e-5, update) at the start of increment 1 on the 64^3 "
                                   "instance" % nits}

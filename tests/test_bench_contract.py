@@ -76,3 +76,4 @@ def test_cpu_baseline_samples_run_on_tiny_instances():
     assert rate > 0 and its >= 3
     t, nits = bench._oracle_newton_step(synth.workload_polycrystal(n=8, ngrains=8))
     assert t > 0 and nits >= 1
+    assert bench._oracle_operator_s(synth.workload_polycrystal(n=8, ngrains=8)) > 0
