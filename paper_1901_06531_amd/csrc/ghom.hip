@@ -285,12 +285,10 @@ int zfwd_grid(const ShapeClass& c) {
 
 template <typename T, int MODE, typename TIN>
 int launch_zfwd(Engine& e, ShapeClass& c, int role, int update_p, const std::string& name) {
-  int grid = 0;
+  const int grid = zfwd_grid<T, MODE>(c);
   with_split(c.nz, [&](auto s) {
     using S = decltype(s);
     using Cfg = ZCfg<T, S::A, S::B, zfwd_ntmin<MODE>()>;
-    const long long nlines = (long long)c.nx * c.ny;
-    grid = (int)((nlines + 2 * Cfg::LP - 1) / (2 * Cfg::LP));
     with_nt<S::A * S::B>(e, [&](auto nt) {
       timed(e, name, [&] {
         hipLaunchKernelGGL((zfwd_batch<T, S::A, S::B, MODE, TIN, decltype(nt)::value>),
