@@ -200,19 +200,27 @@ def test_operator_matches_oracle(shape, law, prec, xproj):
     assert rel_err(out, ref) < (1e-12 if prec == ghom.FP64 else 2e-5)
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32)])
-def test_residual_and_stress_match_oracle(shape):
-    say("residual", shape)
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 16, 32), (12, 16, 9), (9, 27, 12)])
+@pytest.mark.parametrize("law", ["nh", "svk"])
+def test_residual_and_stress_match_oracle(shape, law):
+    say("residual", shape, law)
     g = np.random.default_rng(3)
     F = random_F(shape, g)
     phase, mu, lam, scale = _nh_setup(shape, g)
     Pbar = g.standard_normal(9) * 0.1
     o = go.Oracle(shape)
-    o.set_material_neohookean(phase, mu, lam)
+    if law == "nh":
+        o.set_material_neohookean(phase, mu, lam)
+    else:
+        C = _svk_tables(3, 9)
+        o.set_material_svk(phase, C)
     o.set_stiffness_scale(scale)
     o.set_control(MIXED)
     with ghom.Solver(shape) as s:
-        s.set_material_neohookean(phase, mu, lam)
+        if law == "nh":
+            s.set_material_neohookean(phase, mu, lam)
+        else:
+            s.set_material_svk(phase, C)
         s.set_stiffness_scale(scale)
         s.set_control(MIXED)
         s.load_state(F, 0)
