@@ -375,8 +375,12 @@ def test_fp32_split_sphere16_matches_oracle():
         assert_hist(F, P, ref["F_avg"], ref["P_avg"], 1e-9, p_scale)
 
 
-def test_adjoint_matches_oracle():
-    say("adjoint 12^3")
+@pytest.mark.parametrize("prec", [ghom.FP64, ghom.FP32_SPLIT])
+def test_adjoint_matches_oracle(prec):
+    """FP64 within 1e-8 of the oracle's gradient; FP32-split within 1e-4 (its adjoint CG solve
+    stops at 1e-5 of its right-hand side, the split mode's forcing floor, and the gradient
+    carries an error of that order times the problem's conditioning)."""
+    say("adjoint 12^3, precision", prec)
     shape = (12, 12, 12)
     g = np.random.default_rng(8)
     phase = (g.uniform(size=shape) < 0.3).astype(np.uint16)
@@ -389,10 +393,11 @@ def test_adjoint_matches_oracle():
     a = np.zeros(9)
     a[4] = 1.0
     ref = o.adjoint_grad_scale(a)
-    s, _ = _run_gpu(w)
+    s, _ = _run_gpu(w, prec=prec, forcing=0.0 if prec == ghom.FP64 else 1e-5)
     got = s.adjoint_grad_scale(a)
     s.close()
-    assert rel_err(got, ref) < 1e-8
+    say("  rel err", rel_err(got, ref))
+    assert rel_err(got, ref) < (1e-8 if prec == ghom.FP64 else 1e-4)
 
 
 def test_failure_modes_are_reported():
